@@ -1,0 +1,187 @@
+/*
+ * emt.h -- C ABI of the MI355X 4pi emulsion track finder.
+ *
+ * What it computes (paper, Sec. 2, tracking paragraph and Fig. 4): for each
+ * microscope view, given the 3D grains read from the tomographic focal
+ * planes, every grain pair closer than a seed distance R (any direction,
+ * full solid angle) is a seed; the grains within a radius r of the infinite
+ * line through the seed pair are counted; seeds reaching n_min grains are
+ * candidates; candidates are then taken best first (grain count descending,
+ * then seed input indices ascending), each keeping only grains no earlier
+ * track used, and kept as a track only if n_min grains remain. Each track is
+ * returned with its grain list and a least-squares direction fit.
+ *
+ * Units: grain coordinates are int32 fixed point, 1 unit = 0.01 um. Within a
+ * view the per-axis coordinate span (max - min) must not exceed 2^18 units
+ * (2.62 mm) and a view holds fewer than 2^20 grains. All geometry decisions
+ * are exact integer arithmetic, so track lists do not depend on the device
+ * or on what else is in the batch.
+ *
+ * Threading: a context is not thread-safe; use one per host thread. Calls are
+ * synchronous: when emt_track_views returns, results are on the host.
+ */
+#ifndef EMT_H
+#define EMT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EMT_ABI_VERSION 1u
+
+/* Return codes. */
+#define EMT_OK 0
+#define EMT_EINVAL (-1)    /* null pointer, wrong abi_version, bad parameter   */
+#define EMT_ERANGE (-2)    /* view span > 2^18 units, >= 2^20 grains, R or r
+                              out of range                                    */
+#define EMT_ENOMEM (-3)    /* host or device allocation failed, or a view's
+                              working set exceeds the HBM budget              */
+#define EMT_EDEVICE (-4)   /* HIP error; the context is poisoned: destroy it  */
+#define EMT_EOVERFLOW (-5) /* internal capacity still short after retries     */
+
+/* Flags for emt_config.flags. */
+#define EMT_F_STATS 0x1u           /* time every stage with HIP events       */
+#define EMT_F_FP64_FIT_ALWAYS 0x2u /* solve every fit in FP64                */
+#define EMT_F_DEVICE_PTRS 0x4u     /* emt_view_in.xyz point to device memory */
+
+/* Stage indices of emt_call_stats.ms. */
+#define EMT_STAGE_STAGE 0   /* copy grains in                                */
+#define EMT_STAGE_BIN 1     /* bounding box, cell histogram, scan, scatter   */
+#define EMT_STAGE_SEED 2    /* seed pairs closer than R                      */
+#define EMT_STAGE_COUNT 3   /* grains within r of every seed line           */
+#define EMT_STAGE_MEMBERS 4 /* candidate member lists                       */
+#define EMT_STAGE_MERGE 5   /* exclusive association rounds                 */
+#define EMT_STAGE_FIT 6     /* track order, grain order, fit                */
+#define EMT_STAGE_OUT 7     /* copy tracks out                              */
+#define EMT_N_STAGES 8
+
+/*
+ * Configuration (emt_default_config fills the defaults).
+ *   seed_dist   R in units (default 2500 = 25 um, paper Sec. 2); 1..4096.
+ *   tol_radius  r in units (default 50 = 0.5 um); 0 <= r < R. Inclusive.
+ *   min_grains  n_min (default 8); 2 <= n_min < 2^20. Applied to the count
+ *               and again after exclusive association.
+ *   cell_xy     edge of a hash cell in x and y, units (0 = library choice).
+ *   cell_z      edge of a hash cell in z, units (0 = library choice).
+ *               Cells only steer the work (paper Sec. 3 footnote), never the
+ *               result.
+ *   device      HIP device ordinal.
+ *   flags       EMT_F_* bits.
+ *   hbm_budget  device bytes the context may hold (0 = 80 % of free memory).
+ *   stream      hipStream_t to run on, or NULL for a library-owned stream.
+ */
+typedef struct {
+    uint32_t abi_version;
+    int32_t seed_dist;
+    int32_t tol_radius;
+    int32_t min_grains;
+    int32_t cell_xy;
+    int32_t cell_z;
+    int32_t device;
+    uint32_t flags;
+    uint64_t hbm_budget;
+    void *stream;
+} emt_config;
+
+/* One view in. xyz: n_grains x 3 int32 (x, y, z interleaved), owned by the
+ * caller, read only during the call; a host pointer unless the context was
+ * created with EMT_F_DEVICE_PTRS. n_grains may be 0. */
+typedef struct {
+    const int32_t *xyz;
+    uint32_t n_grains;
+    uint32_t reserved;
+    uint64_t view_id;
+} emt_view_in;
+
+/* One track. seed: input indices (i < j) of the accepted seed pair.
+ * grain_offset/n_grains: slice of emt_view_out.grains holding the track's
+ * grains as input indices, ordered by (g_k - g_i).(g_j - g_i), then index.
+ * axis: 0, 1, 2 for x, y, z, the axis of largest spread; slope: d(b)/d(axis)
+ * and d(c)/d(axis) for the other two axes b < c; dir: unit direction with
+ * dir.z > 0 (else dir.y > 0, else dir.x > 0); centroid in um; t_begin and
+ * t_end: extent of the grains along dir about the centroid, um.
+ * fit_fp64: 1 if the slopes were solved in FP64 (axis == z or RMS spread
+ * along axis < 5 um or EMT_F_FP64_FIT_ALWAYS); degenerate: 1 if all grains
+ * of the track coincide (dir is then the seed direction). */
+typedef struct {
+    uint32_t seed[2];
+    uint32_t grain_offset;
+    uint32_t n_grains;
+    uint32_t axis;
+    uint32_t fit_fp64;
+    uint32_t degenerate;
+    float slope[2];
+    float dir[3];
+    float centroid[3];
+    float t_begin;
+    float t_end;
+} emt_track;
+
+typedef struct {
+    uint64_t n_seeds;      /* pairs closer than R                   */
+    uint32_t n_candidates; /* seeds reaching n_min                  */
+    uint32_t n_tracks;
+} emt_view_stats;
+
+/* Results of one view, owned by the context and valid until the next call
+ * on it or emt_destroy. */
+typedef struct {
+    uint64_t view_id;
+    uint32_t n_tracks;
+    uint32_t n_track_grains;
+    const emt_track *tracks;
+    const uint32_t *grains;
+    emt_view_stats stats;
+} emt_view_out;
+
+/* Whole-call statistics of the last emt_track_views on a context. */
+typedef struct {
+    uint64_t n_seeds;
+    uint64_t n_tests;      /* grains examined while counting             */
+    uint64_t n_hits;       /* sum over seeds of the grain count          */
+    uint32_t n_candidates;
+    uint32_t n_tracks;
+    uint32_t merge_rounds;
+    uint32_t n_fp64_fits;
+    uint32_t retries;      /* re-runs after a capacity overflow          */
+    uint32_t n_views;
+    float ms[EMT_N_STAGES]; /* device time per stage (EMT_F_STATS), else 0 */
+    float ms_total;
+} emt_call_stats;
+
+/* Opaque context: device buffers, stream and events of one tracker. */
+typedef struct emt_ctx emt_ctx;
+
+/* Fill *cfg with defaults (abi_version set). */
+void emt_default_config(emt_config *cfg);
+
+/* Check a configuration and host-resident views without touching a device.
+ * Returns EMT_OK, EMT_EINVAL or EMT_ERANGE. views may be NULL if
+ * n_views == 0. Views are checked only when they are host pointers. */
+int emt_validate(const emt_config *cfg, const emt_view_in *views,
+                 uint32_t n_views);
+
+/* Create a context on cfg->device. *out is set to NULL on failure. */
+int emt_create(const emt_config *cfg, emt_ctx **out);
+
+/* Track n_views views. n_views == 1 runs one view per launch sequence;
+ * n_views > 1 runs all views through the same launches. out must hold
+ * n_views entries. On error no output is valid. */
+int emt_track_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views,
+                    emt_view_out *out);
+
+/* Statistics of the last successful emt_track_views. */
+int emt_last_stats(emt_ctx *ctx, emt_call_stats *stats);
+
+/* Release a context; NULL is ignored. */
+void emt_destroy(emt_ctx *ctx);
+
+/* Static text for a return code. */
+const char *emt_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,640 @@
+// api.hip -- host implementation of the C ABI declared in include/emt.h.
+//
+// A context owns a stream, device buffers sized by capacities that only
+// grow, pinned host buffers for staging and results, and timing events.
+// One call packs the views, runs the stage sequence of kernels.hip on the
+// stream, and copies the tracks back. Device-side counters keep counting
+// past a capacity, so an overflow is repaired by one re-run with the exact
+// sizes the first run reported.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "emt_dev.h"
+
+using namespace emt;
+
+namespace {
+
+constexpr uint32_t kKnownFlags = EMT_F_STATS | EMT_F_FP64_FIT_ALWAYS | EMT_F_DEVICE_PTRS;
+constexpr int kDefaultCellXY = 750;  // 7.5 um, the paper's 32-pixel hash cell
+constexpr int kDefaultCellZ = 500;
+constexpr int kMaxAttempts = 4;
+constexpr int kRoundChunk = 8;
+
+struct DevArena {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct emt_ctx {
+    emt_config cfg{};
+    Params P{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool poisoned = false;
+    hipEvent_t ev[EMT_N_STAGES + 1] = {};
+    size_t budget = 0;
+    size_t held = 0;
+
+    // device buffers, grown on demand
+    DevArena grain_buf, cell_buf, seed_buf, cand_buf, mem_buf, view_buf, misc_buf;
+    DevPtrs d{};
+    // capacities the buffers currently hold
+    uint32_t cap_n = 0, cap_cells = 0, cap_views = 0, cap_cand = 0, cap_mem = 0;
+    unsigned long long cap_seeds = 0;
+    // capacities learned from earlier calls
+    double seeds_per_grain = 256.0, cand_per_grain = 8.0, mem_per_cand = 24.0;
+
+    // pinned host buffers
+    int32_t *h_xyz = nullptr;
+    size_t h_xyz_cap = 0;
+    ViewGrid *h_grids = nullptr;
+    unsigned long long *h_view_seeds = nullptr;
+    uint32_t *h_view_cand = nullptr, *h_view_ntr = nullptr, *h_view_tr_off = nullptr;
+    uint32_t h_views_cap = 0;
+    Counters *h_cnt = nullptr;
+    emt_track *h_tracks = nullptr;
+    size_t h_tracks_cap = 0;
+    uint32_t *h_grains = nullptr;
+    size_t h_grains_cap = 0;
+
+    emt_call_stats last{};
+};
+
+namespace {
+
+int check_config(const emt_config *c) {
+    if (!c) return EMT_EINVAL;
+    if (c->abi_version != EMT_ABI_VERSION) return EMT_EINVAL;
+    if ((c->flags & ~kKnownFlags) != 0) return EMT_EINVAL;
+    if (c->cell_xy < 0 || c->cell_z < 0) return EMT_EINVAL;
+    if (c->device < 0) return EMT_EINVAL;
+    if (c->seed_dist < 1 || c->seed_dist > kRMax) return EMT_ERANGE;
+    if (c->tol_radius < 0 || c->tol_radius >= c->seed_dist) return EMT_ERANGE;
+    if (c->min_grains < 2 || (uint32_t)c->min_grains >= kNMax) return EMT_ERANGE;
+    if (c->cell_xy > kSpanMax || c->cell_z > kSpanMax) return EMT_ERANGE;
+    return EMT_OK;
+}
+
+int check_views(const emt_config *c, const emt_view_in *v, uint32_t nv) {
+    if (nv > 0 && !v) return EMT_EINVAL;
+    unsigned long long total = 0;
+    for (uint32_t i = 0; i < nv; ++i) {
+        if (v[i].n_grains > 0 && !v[i].xyz) return EMT_EINVAL;
+        if (v[i].n_grains >= kNMax) return EMT_ERANGE;
+        total += v[i].n_grains;
+        if (c->flags & EMT_F_DEVICE_PTRS) continue;
+        const int32_t *x = v[i].xyz;
+        for (int m = 0; m < 3 && v[i].n_grains; ++m) {
+            int32_t lo = x[m], hi = x[m];
+            for (uint32_t k = 1; k < v[i].n_grains; ++k) {
+                const int32_t q = x[3 * (size_t)k + m];
+                lo = q < lo ? q : lo;
+                hi = q > hi ? q : hi;
+            }
+            if ((long long)hi - (long long)lo > kSpanMax) return EMT_ERANGE;
+        }
+    }
+    if (total >= (1ull << 31)) return EMT_ERANGE;
+    return EMT_OK;
+}
+
+template <class T>
+T *carve(char *&p, size_t n) {
+    T *r = reinterpret_cast<T *>(p);
+    p += ((n * sizeof(T) + 255) / 256) * 256;
+    return r;
+}
+
+template <class T>
+size_t bytes_of(size_t n) {
+    return ((n * sizeof(T) + 255) / 256) * 256;
+}
+
+#define HIP_OK(expr)                        \
+    do {                                    \
+        if ((expr) != hipSuccess) {         \
+            ctx->poisoned = true;           \
+            return EMT_EDEVICE;             \
+        }                                   \
+    } while (0)
+
+int arena(emt_ctx *ctx, DevArena &a, size_t bytes) {
+    if (a.bytes >= bytes) return EMT_OK;
+    if (a.p) {
+        if (hipFree(a.p) != hipSuccess) {
+            ctx->poisoned = true;
+            return EMT_EDEVICE;
+        }
+        ctx->held -= a.bytes;
+        a.p = nullptr;
+        a.bytes = 0;
+    }
+    if (ctx->held + bytes > ctx->budget) return EMT_ENOMEM;
+    if (hipMalloc(&a.p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return EMT_ENOMEM;
+    }
+    a.bytes = bytes;
+    ctx->held += bytes;
+    return EMT_OK;
+}
+
+template <class T>
+int pinned(emt_ctx *ctx, T *&p, size_t &cap, size_t n) {
+    if (cap >= n && p) return EMT_OK;
+    if (p) {
+        if (hipHostFree(p) != hipSuccess) {
+            ctx->poisoned = true;
+            return EMT_EDEVICE;
+        }
+        p = nullptr;
+        cap = 0;
+    }
+    size_t want = std::max<size_t>(n, 1024);
+    want += want / 4;
+    if (hipHostMalloc((void **)&p, want * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return EMT_ENOMEM;
+    }
+    cap = want;
+    return EMT_OK;
+}
+
+// Make every buffer hold the capacities in c, carve the pointer table, and
+// raise c to what the buffers hold.
+int ensure(emt_ctx *ctx, Caps &c) {
+    int rc;
+    DevPtrs &d = ctx->d;
+    if (c.n_total > ctx->cap_n || !ctx->grain_buf.p) {
+        const size_t n = std::max<uint32_t>(c.n_total, 1024);
+        const size_t b = bytes_of<int32_t>(3 * n) + 3 * bytes_of<uint32_t>(n) + bytes_of<int4>(n) +
+                         bytes_of<uint8_t>(n) + bytes_of<unsigned long long>(n);
+        if ((rc = arena(ctx, ctx->grain_buf, b))) return rc;
+        char *p = (char *)ctx->grain_buf.p;
+        d.xyz = carve<int32_t>(p, 3 * n);
+        d.view_of = carve<uint32_t>(p, n);
+        d.cell_of = carve<uint32_t>(p, n);
+        d.rank = carve<uint32_t>(p, n);
+        d.sg = carve<int4>(p, n);
+        d.used = carve<uint8_t>(p, n);
+        d.owner = carve<unsigned long long>(p, n);
+        ctx->cap_n = (uint32_t)n;
+    }
+    if (c.seed_cap > ctx->cap_seeds || !ctx->seed_buf.p) {
+        if ((rc = arena(ctx, ctx->seed_buf, bytes_of<uint2>(c.seed_cap)))) return rc;
+        d.seeds = (uint2 *)ctx->seed_buf.p;
+        ctx->cap_seeds = c.seed_cap;
+    }
+    if (c.cand_cap > ctx->cap_cand || !ctx->cand_buf.p) {
+        const size_t n = c.cand_cap;
+        const size_t b = bytes_of<Cand>(n) + bytes_of<unsigned long long>(n) +
+                         6 * bytes_of<uint32_t>(n + 1) + 4 * bytes_of<uint32_t>(n) +
+                         bytes_of<uint8_t>(n) + bytes_of<emt_track>(n);
+        if ((rc = arena(ctx, ctx->cand_buf, b))) return rc;
+        char *p = (char *)ctx->cand_buf.p;
+        d.cand = carve<Cand>(p, n);
+        d.key = carve<unsigned long long>(p, n);
+        d.cand_n = carve<uint32_t>(p, n + 1);
+        d.mem_off = carve<uint32_t>(p, n + 1);
+        d.tg_n = carve<uint32_t>(p, n + 1);
+        d.tg_off = carve<uint32_t>(p, n + 1);
+        d.act[0] = carve<uint32_t>(p, n + 1);
+        d.act[1] = carve<uint32_t>(p, n + 1);
+        d.mcount = carve<uint32_t>(p, n);
+        d.acc = carve<uint32_t>(p, n);
+        d.grouped = carve<uint32_t>(p, n);
+        d.track_cand = carve<uint32_t>(p, n);
+        d.status = carve<uint8_t>(p, n);
+        d.tracks = carve<emt_track>(p, n);
+        ctx->cap_cand = (uint32_t)n;
+    }
+    if (c.mem_cap > ctx->cap_mem || !ctx->mem_buf.p) {
+        const size_t n = c.mem_cap;
+        const size_t b = 3 * bytes_of<uint32_t>(n) + bytes_of<uint8_t>(n) + bytes_of<long long>(n);
+        if ((rc = arena(ctx, ctx->mem_buf, b))) return rc;
+        char *p = (char *)ctx->mem_buf.p;
+        d.members = carve<uint32_t>(p, n);
+        d.tord = carve<uint32_t>(p, n);
+        d.out_grains = carve<uint32_t>(p, n);
+        d.taken = carve<uint8_t>(p, n);
+        d.tvals = carve<long long>(p, n);
+        ctx->cap_mem = (uint32_t)n;
+    }
+    c.seed_cap = std::max<unsigned long long>(c.seed_cap, ctx->cap_seeds);
+    c.cand_cap = std::max(c.cand_cap, ctx->cap_cand);
+    c.mem_cap = std::max(c.mem_cap, ctx->cap_mem);
+    const uint32_t scan_cap = std::max<uint32_t>(c.n_cells, c.cand_cap) + 1;
+    if (c.n_cells > ctx->cap_cells || c.cand_cap + 1 > ctx->cap_cells || !ctx->cell_buf.p) {
+        const size_t n = std::max<uint32_t>(scan_cap, 1u << 16);
+        const size_t b = 2 * bytes_of<uint32_t>(n) + bytes_of<uint32_t>(scan_scratch_words((uint32_t)n));
+        if ((rc = arena(ctx, ctx->cell_buf, b))) return rc;
+        char *p = (char *)ctx->cell_buf.p;
+        d.cell_count = carve<uint32_t>(p, n);
+        d.cell_start = carve<uint32_t>(p, n);
+        d.scan_part = carve<uint32_t>(p, scan_scratch_words((uint32_t)n));
+        ctx->cap_cells = (uint32_t)n;
+    }
+    if (c.n_views > ctx->cap_views || !ctx->view_buf.p) {
+        const size_t n = std::max<uint32_t>(c.n_views, 64);
+        const size_t b = bytes_of<ViewGrid>(n) + bytes_of<unsigned long long>(n) +
+                         4 * bytes_of<uint32_t>(n + 1) + bytes_of<Counters>(1);
+        if ((rc = arena(ctx, ctx->view_buf, b))) return rc;
+        char *p = (char *)ctx->view_buf.p;
+        d.grids = carve<ViewGrid>(p, n);
+        d.view_seeds = carve<unsigned long long>(p, n);
+        d.view_cand = carve<uint32_t>(p, n + 1);
+        d.view_ntr = carve<uint32_t>(p, n + 1);
+        d.view_tr_off = carve<uint32_t>(p, n + 1);
+        d.view_cursor = carve<uint32_t>(p, n + 1);
+        d.cnt = carve<Counters>(p, 1);
+        ctx->cap_views = (uint32_t)n;
+        // matching pinned host arrays
+        size_t cap = 0;
+        if (ctx->h_grids) {
+            (void)hipHostFree(ctx->h_grids);
+            (void)hipHostFree(ctx->h_view_seeds);
+            (void)hipHostFree(ctx->h_view_cand);
+            (void)hipHostFree(ctx->h_view_ntr);
+            (void)hipHostFree(ctx->h_view_tr_off);
+            ctx->h_grids = nullptr;
+        }
+        if ((rc = pinned(ctx, ctx->h_grids, cap, n))) return rc;
+        cap = 0;
+        if ((rc = pinned(ctx, ctx->h_view_seeds, cap, n))) return rc;
+        cap = 0;
+        if ((rc = pinned(ctx, ctx->h_view_cand, cap, n + 1))) return rc;
+        cap = 0;
+        if ((rc = pinned(ctx, ctx->h_view_ntr, cap, n + 1))) return rc;
+        cap = 0;
+        if ((rc = pinned(ctx, ctx->h_view_tr_off, cap, n + 1))) return rc;
+        ctx->h_views_cap = (uint32_t)n;
+    }
+    if (!ctx->h_cnt) {
+        size_t cap = 0;
+        if ((rc = pinned(ctx, ctx->h_cnt, cap, 1))) return rc;
+    }
+    return EMT_OK;
+}
+
+void record(emt_ctx *ctx, int i) {
+    if (ctx->cfg.flags & EMT_F_STATS) (void)hipEventRecord(ctx->ev[i], ctx->stream);
+}
+
+uint32_t clamp_u32(double x) {
+    if (x < 1024.0) return 1024u;
+    if (x > 2147483647.0) return 2147483647u;
+    return (uint32_t)x;
+}
+
+// One attempt at the whole batch. Returns EMT_OK, EMT_EOVERFLOW (caps too
+// small: ctx->h_cnt holds the needs) or an error.
+int run_once(emt_ctx *ctx, const emt_view_in *views, uint32_t nv, const Caps &c,
+             bool *overflow) {
+    DevPtrs &d = ctx->d;
+    hipStream_t s = ctx->stream;
+    *overflow = false;
+    record(ctx, 0);
+    // stage the grains
+    const bool dev = (ctx->cfg.flags & EMT_F_DEVICE_PTRS) != 0;
+    DevPtrs run = d;
+    if (dev && nv == 1) {
+        run.xyz = views[0].xyz;
+    } else if (dev) {
+        for (uint32_t v = 0; v < nv; ++v) {
+            if (!views[v].n_grains) continue;
+            HIP_OK(hipMemcpyAsync((void *)(d.xyz + 3 * (size_t)ctx->h_grids[v].grain_off),
+                                  views[v].xyz, 12 * (size_t)views[v].n_grains,
+                                  hipMemcpyDeviceToDevice, s));
+        }
+    } else {
+        HIP_OK(hipMemcpyAsync((void *)d.xyz, ctx->h_xyz, 12 * (size_t)c.n_total,
+                              hipMemcpyHostToDevice, s));
+    }
+    HIP_OK(hipMemcpyAsync(d.grids, ctx->h_grids, sizeof(ViewGrid) * nv, hipMemcpyHostToDevice, s));
+    record(ctx, 1);
+    launch_prepare(run, c, ctx->P, s);
+    launch_bin(run, c, ctx->P, s);
+    record(ctx, 2);
+    launch_seeds(run, c, ctx->P, s);
+    record(ctx, 3);
+    launch_count(run, c, ctx->P, s);
+    record(ctx, 4);
+    launch_members(run, c, ctx->P, s);
+    record(ctx, 5);
+    launch_merge_init(run, c, ctx->P, s);
+    int round = 0;
+    for (;;) {
+        for (int k = 0; k < kRoundChunk; ++k, ++round) launch_merge_round(run, c, ctx->P, round, s);
+        HIP_OK(hipMemcpyAsync(ctx->h_cnt, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        const Counters &h = *ctx->h_cnt;
+        if (h.n_seeds > c.seed_cap || h.n_cand > c.cand_cap || h.n_members > c.mem_cap) {
+            *overflow = true;
+            return EMT_EOVERFLOW;
+        }
+        if (h.n_act[round & 1] == 0) break;
+    }
+    record(ctx, 6);
+    launch_fit(run, c, ctx->P, s);
+    record(ctx, 7);
+    HIP_OK(hipMemcpyAsync(ctx->h_cnt, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(ctx->h_view_seeds, d.view_seeds, sizeof(unsigned long long) * nv,
+                          hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(ctx->h_view_cand, d.view_cand, sizeof(uint32_t) * nv,
+                          hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(ctx->h_view_ntr, d.view_ntr, sizeof(uint32_t) * nv,
+                          hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(ctx->h_view_tr_off, d.view_tr_off, sizeof(uint32_t) * (nv + 1),
+                          hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(ctx->h_grids, d.grids, sizeof(ViewGrid) * nv, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const uint32_t nt = ctx->h_cnt->n_acc, ng = ctx->h_cnt->n_track_grains;
+    int rc;
+    if ((rc = pinned(ctx, ctx->h_tracks, ctx->h_tracks_cap, nt))) return rc;
+    if ((rc = pinned(ctx, ctx->h_grains, ctx->h_grains_cap, ng))) return rc;
+    if (nt) {
+        HIP_OK(hipMemcpyAsync(ctx->h_tracks, d.tracks, sizeof(emt_track) * nt,
+                              hipMemcpyDeviceToHost, s));
+    }
+    if (ng) {
+        HIP_OK(hipMemcpyAsync(ctx->h_grains, d.out_grains, sizeof(uint32_t) * ng,
+                              hipMemcpyDeviceToHost, s));
+    }
+    record(ctx, 8);
+    HIP_OK(hipStreamSynchronize(s));
+    return EMT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void emt_default_config(emt_config *cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->abi_version = EMT_ABI_VERSION;
+    cfg->seed_dist = 2500;
+    cfg->tol_radius = 50;
+    cfg->min_grains = 8;
+    cfg->cell_xy = 0;
+    cfg->cell_z = 0;
+    cfg->device = 0;
+    cfg->flags = 0;
+    cfg->hbm_budget = 0;
+    cfg->stream = nullptr;
+}
+
+int emt_validate(const emt_config *cfg, const emt_view_in *views, uint32_t n_views) {
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    return check_views(cfg, views, n_views);
+}
+
+const char *emt_strerror(int code) {
+    switch (code) {
+        case EMT_OK: return "ok";
+        case EMT_EINVAL: return "invalid argument";
+        case EMT_ERANGE: return "value out of range (span, grain count, R or r)";
+        case EMT_ENOMEM: return "out of memory or HBM budget";
+        case EMT_EDEVICE: return "HIP device error (context poisoned)";
+        case EMT_EOVERFLOW: return "internal capacity overflow after retries";
+        default: return "unknown error";
+    }
+}
+
+int emt_create(const emt_config *cfg, emt_ctx **out) {
+    if (!out) return EMT_EINVAL;
+    *out = nullptr;
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device >= ndev) {
+        (void)hipGetLastError();
+        return EMT_EDEVICE;
+    }
+    if (hipSetDevice(cfg->device) != hipSuccess) return EMT_EDEVICE;
+    emt_ctx *ctx = new (std::nothrow) emt_ctx();
+    if (!ctx) return EMT_ENOMEM;
+    ctx->cfg = *cfg;
+    ctx->P.R = cfg->seed_dist;
+    ctx->P.r = cfg->tol_radius;
+    ctx->P.n_min = cfg->min_grains;
+    ctx->P.slab_x = 1;
+    ctx->P.cell_req[0] = cfg->cell_xy ? cfg->cell_xy : kDefaultCellXY;
+    ctx->P.cell_req[1] = cfg->cell_xy ? cfg->cell_xy : kDefaultCellXY;
+    ctx->P.cell_req[2] = cfg->cell_z ? cfg->cell_z : kDefaultCellZ;
+    ctx->P.flags = cfg->flags;
+    if (const char *e = std::getenv("EMT_SLAB_X")) ctx->P.slab_x = std::max(1, std::atoi(e));
+    // Test hook: start from tiny capacities so the first call overflows and
+    // the retry path runs.
+    if (const char *e = std::getenv("EMT_INITIAL_CAPS")) {
+        if (std::strcmp(e, "tiny") == 0) {
+            ctx->seeds_per_grain = 0.5;
+            ctx->cand_per_grain = 0.01;
+            ctx->mem_per_cand = 1.0;
+        }
+    }
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        delete ctx;
+        return EMT_EDEVICE;
+    }
+    ctx->budget = cfg->hbm_budget ? (size_t)cfg->hbm_budget : (size_t)(0.8 * (double)free_b);
+    if (cfg->stream) {
+        ctx->stream = (hipStream_t)cfg->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return EMT_EDEVICE;
+        }
+        ctx->own_stream = true;
+    }
+    for (int i = 0; i <= EMT_N_STAGES; ++i) {
+        if (hipEventCreate(&ctx->ev[i]) != hipSuccess) {
+            emt_destroy(ctx);
+            return EMT_EDEVICE;
+        }
+    }
+    *out = ctx;
+    return EMT_OK;
+}
+
+int emt_track_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views, emt_view_out *out) {
+    if (!ctx) return EMT_EINVAL;
+    if (ctx->poisoned) return EMT_EDEVICE;
+    if (n_views > 0 && !out) return EMT_EINVAL;
+    int rc = check_views(&ctx->cfg, views, n_views);
+    if (rc) return rc;
+    if (n_views == 0) return EMT_OK;
+    if (hipSetDevice(ctx->cfg.device) != hipSuccess) {
+        ctx->poisoned = true;
+        return EMT_EDEVICE;
+    }
+    // batch geometry
+    Caps c{};
+    c.n_views = n_views;
+    unsigned long long n_total = 0, n_cells = 0;
+    uint32_t max_n = 0;
+    for (uint32_t v = 0; v < n_views; ++v) {
+        n_total += views[v].n_grains;
+        n_cells += 4ull * views[v].n_grains + 4096 + 1;
+        max_n = std::max(max_n, views[v].n_grains);
+    }
+    if (n_cells >= (1ull << 31)) return EMT_ERANGE;
+    c.n_total = (uint32_t)n_total;
+    c.n_cells = (uint32_t)n_cells;
+    c.max_view_n = max_n;
+    c.seed_cap = std::max<unsigned long long>(
+        4096, (unsigned long long)(ctx->seeds_per_grain * (double)n_total));
+    c.cand_cap = clamp_u32(ctx->cand_per_grain * (double)n_total);
+    c.mem_cap = clamp_u32(ctx->mem_per_cand * (double)c.cand_cap);
+
+    // ensure the view tables exist before filling pinned staging
+    if ((rc = ensure(ctx, c))) return rc;
+    if (!(ctx->cfg.flags & EMT_F_DEVICE_PTRS)) {
+        if ((rc = pinned(ctx, ctx->h_xyz, ctx->h_xyz_cap, 3 * (size_t)std::max<uint32_t>(c.n_total, 1))))
+            return rc;
+    }
+    if (!(ctx->cfg.flags & EMT_F_DEVICE_PTRS)) {
+        uint32_t goff = 0;
+        for (uint32_t v = 0; v < n_views; ++v) {
+            if (views[v].n_grains)
+                std::memcpy(ctx->h_xyz + 3 * (size_t)goff, views[v].xyz,
+                            12 * (size_t)views[v].n_grains);
+            goff += views[v].n_grains;
+        }
+    }
+
+    uint32_t retries = 0;
+    for (int attempt = 0;; ++attempt) {
+        if ((rc = ensure(ctx, c))) return rc;
+        bool overflow = false;
+        // ViewGrid staging is overwritten by the read-back: refill per attempt
+        uint32_t go = 0, co = 0;
+        for (uint32_t v = 0; v < n_views; ++v) {
+            ViewGrid &G = ctx->h_grids[v];
+            G = ViewGrid{};
+            for (int m = 0; m < 3; ++m) {
+                G.lo[m] = INT32_MAX;
+                G.hi[m] = INT32_MIN;
+            }
+            G.grain_off = go;
+            G.n = views[v].n_grains;
+            G.cell_off = co;
+            G.cell_cap = 4u * views[v].n_grains + 4096u;
+            go += G.n;
+            co += G.cell_cap + 1;
+        }
+        rc = run_once(ctx, views, n_views, c, &overflow);
+        if (rc == EMT_OK) break;
+        if (!overflow) return rc;
+        if (attempt + 1 >= kMaxAttempts) return EMT_EOVERFLOW;
+        ++retries;
+        const Counters h = *ctx->h_cnt;
+        // the counters are exact for the stage that overflowed; later stages
+        // are sized from the per-grain and per-candidate ratios
+        if (h.n_seeds > c.seed_cap) {
+            c.seed_cap = h.n_seeds + h.n_seeds / 8 + 1024;
+            ctx->seeds_per_grain = std::max(ctx->seeds_per_grain, 1.125 * (double)h.n_seeds / std::max(1.0, (double)n_total));
+        }
+        if (h.n_cand > c.cand_cap) {
+            c.cand_cap = clamp_u32((double)h.n_cand * 1.125 + 1024);
+            ctx->cand_per_grain = std::max(ctx->cand_per_grain, 1.125 * (double)h.n_cand / std::max(1.0, (double)n_total));
+        }
+        if (h.n_members > c.mem_cap || h.n_cand > c.cand_cap) {
+            const double per = h.n_cand ? (double)h.n_members / (double)h.n_cand : ctx->mem_per_cand;
+            ctx->mem_per_cand = std::max(ctx->mem_per_cand, 1.125 * per);
+            c.mem_cap = clamp_u32(std::max((double)h.n_members * 1.125 + 1024,
+                                           ctx->mem_per_cand * (double)c.cand_cap));
+        }
+    }
+
+    // device-side rejections (span of device-resident views)
+    for (uint32_t v = 0; v < n_views; ++v)
+        if (ctx->h_grids[v].err) return EMT_ERANGE;
+    if (ctx->h_cnt->err & 2u) {
+        // member lists disagreed with the counts: an internal fault
+        ctx->poisoned = true;
+        return EMT_EDEVICE;
+    }
+
+    // outputs: per-view slices of the track and grain arrays
+    const Counters &h = *ctx->h_cnt;
+    for (uint32_t v = 0; v < n_views; ++v) {
+        emt_view_out &o = out[v];
+        const uint32_t t0 = ctx->h_view_tr_off[v], nt = ctx->h_view_ntr[v];
+        o.view_id = views[v].view_id;
+        o.n_tracks = nt;
+        o.tracks = ctx->h_tracks + t0;
+        const uint32_t g0 = nt ? ctx->h_tracks[t0].grain_offset : 0;
+        uint32_t ng = 0;
+        for (uint32_t t = 0; t < nt; ++t) {
+            emt_track &tr = ctx->h_tracks[t0 + t];
+            tr.grain_offset -= g0;
+            ng += tr.n_grains;
+        }
+        o.n_track_grains = ng;
+        o.grains = ctx->h_grains + g0;
+        o.stats.n_seeds = ctx->h_view_seeds[v];
+        o.stats.n_candidates = ctx->h_view_cand[v];
+        o.stats.n_tracks = nt;
+    }
+    emt_call_stats &st = ctx->last;
+    st = emt_call_stats{};
+    st.n_seeds = h.n_seeds;
+    st.n_tests = h.tests;
+    st.n_hits = h.hits;
+    st.n_candidates = h.n_cand;
+    st.n_tracks = h.n_acc;
+    st.merge_rounds = h.rounds;
+    st.n_fp64_fits = h.n_fp64;
+    st.retries = retries;
+    st.n_views = n_views;
+    if (ctx->cfg.flags & EMT_F_STATS) {
+        float tot = 0.0f;
+        for (int i = 0; i < EMT_N_STAGES; ++i) {
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]);
+            st.ms[i] = ms;
+            tot += ms;
+        }
+        st.ms_total = tot;
+    }
+    return EMT_OK;
+}
+
+int emt_last_stats(emt_ctx *ctx, emt_call_stats *stats) {
+    if (!ctx || !stats) return EMT_EINVAL;
+    *stats = ctx->last;
+    return EMT_OK;
+}
+
+void emt_destroy(emt_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->cfg.device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    DevArena *arenas[] = {&ctx->grain_buf, &ctx->cell_buf, &ctx->seed_buf, &ctx->cand_buf,
+                          &ctx->mem_buf, &ctx->view_buf, &ctx->misc_buf};
+    for (DevArena *a : arenas)
+        if (a->p) (void)hipFree(a->p);
+    void *hosts[] = {ctx->h_xyz, ctx->h_grids, ctx->h_view_seeds, ctx->h_view_cand,
+                     ctx->h_view_ntr, ctx->h_view_tr_off, ctx->h_cnt, ctx->h_tracks,
+                     ctx->h_grains};
+    for (void *p : hosts)
+        if (p) (void)hipHostFree(p);
+    for (int i = 0; i <= EMT_N_STAGES; ++i)
+        if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+// emt_dev.h -- device-side structures and launchers of the track finder.
+//
+// Library-internal: shared by the kernels (kernels.hip) and the host
+// implementation of the C ABI (api.hip). Nothing here is part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "emt.h"
+
+namespace emt {
+
+constexpr int kSpanMax = 1 << 18;  // per-axis coordinate span limit (units)
+constexpr uint32_t kNMax = 1u << 20;
+constexpr int kRMax = 4096;
+constexpr int kBlock = 256;
+
+// Per view. Host fills grain_off, n, cell_off, cell_cap and resets lo/hi;
+// the device fills the rest (bounding box, then cell geometry).
+struct ViewGrid {
+    int32_t lo[3];       // bounding box min (absolute units) = grid origin
+    int32_t hi[3];       // bounding box max
+    int32_t cell[3];     // cell edge per axis (units)
+    int32_t dims[3];     // cells per axis
+    uint32_t grain_off;  // first grain of the view in the packed arrays
+    uint32_t n;          // grains of the view (0 if rejected on device)
+    uint32_t cell_off;   // first cell of the view in cell_start
+    uint32_t cell_cap;   // cells the view may use
+    int32_t err;         // 1: coordinate span above kSpanMax
+    int32_t pad[3];
+};
+
+struct Params {
+    int32_t R, r, n_min, slab_x;
+    int32_t cell_req[3];
+    uint32_t flags;
+};
+
+// Device counters of one call. Totals keep counting past capacities so the
+// host learns what a retry needs.
+struct Counters {
+    unsigned long long n_seeds;
+    unsigned long long tests;
+    unsigned long long hits;
+    uint32_t n_cand;
+    uint32_t n_members;
+    uint32_t n_act[2];
+    uint32_t n_acc;
+    uint32_t n_track_grains;
+    uint32_t rounds;
+    uint32_t n_fp64;
+    uint32_t err;
+    uint32_t pad[3];
+};
+
+struct Cand {
+    uint32_t p, q;  // sorted positions of the seed grains
+    uint32_t n;     // grains within r of the seed line
+    uint32_t v;     // view
+};
+
+// Candidate priority: smaller key = taken earlier. Grain count descending,
+// then the seed's input indices i, j ascending (all below 2^20).
+__host__ __device__ inline unsigned long long cand_key(uint32_t n, uint32_t i,
+                                                       uint32_t j) {
+    return ((unsigned long long)(kNMax - 1u - n) << 40) |
+           ((unsigned long long)i << 20) | (unsigned long long)j;
+}
+
+enum : uint8_t { kUndecided = 0, kAccepted = 1, kRejected = 2 };
+
+// All device buffers of one call, as raw pointers.
+struct DevPtrs {
+    const int32_t *xyz;   // packed input, N x 3
+    ViewGrid *grids;
+    uint32_t *view_of;    // N
+    uint32_t *cell_of;    // N
+    uint32_t *rank;       // N
+    uint32_t *cell_count; // C
+    uint32_t *cell_start; // C
+    int4 *sg;             // N sorted grains: x, y, z relative to lo; w = input index
+    uint2 *seeds;         // seed_cap
+    Cand *cand;           // cand_cap
+    unsigned long long *key;  // cand_cap
+    uint32_t *cand_n;     // cand_cap + 1
+    uint32_t *mem_off;    // cand_cap + 1
+    uint32_t *members;    // mem_cap
+    uint8_t *taken;       // mem_cap
+    uint8_t *status;      // cand_cap
+    uint32_t *mcount;     // cand_cap
+    uint8_t *used;        // N
+    unsigned long long *owner;  // N
+    uint32_t *act[2];     // cand_cap each
+    uint32_t *acc;        // cand_cap
+    uint32_t *grouped;    // cand_cap
+    uint32_t *track_cand; // cand_cap
+    uint32_t *tg_n;       // cand_cap + 1
+    uint32_t *tg_off;     // cand_cap + 1
+    long long *tvals;     // mem_cap
+    uint32_t *tord;       // mem_cap
+    emt_track *tracks;    // cand_cap
+    uint32_t *out_grains; // mem_cap
+    unsigned long long *view_seeds;  // V
+    uint32_t *view_cand;  // V
+    uint32_t *view_ntr;   // V
+    uint32_t *view_tr_off;  // V + 1
+    uint32_t *view_cursor;  // V
+    uint32_t *scan_part;  // scan scratch
+    Counters *cnt;
+};
+
+struct Caps {
+    uint32_t n_total;         // grains in the batch
+    uint32_t n_views;
+    uint32_t n_cells;         // C
+    uint32_t max_view_n;
+    unsigned long long seed_cap;
+    uint32_t cand_cap;
+    uint32_t mem_cap;
+};
+
+// Launchers (kernels.hip). All run on `s` and only enqueue work.
+void launch_prepare(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
+void launch_bin(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
+void launch_seeds(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
+void launch_count(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
+void launch_members(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
+void launch_merge_init(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
+void launch_merge_round(const DevPtrs &d, const Caps &c, const Params &P, int round,
+                        hipStream_t s);
+void launch_fit(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
+
+size_t scan_scratch_words(uint32_t n_cap);
+
+}  // namespace emt

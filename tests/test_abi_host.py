@@ -1,0 +1,136 @@
+"""Host-only checks of the C ABI: the library loads without a GPU, exports
+every function the header declares, agrees with the header on struct layout,
+and rejects bad configurations and views before touching a device."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "emt.h")
+
+
+@pytest.fixture(scope="module")
+def emt():
+    from paper_1311_5334_amd import emt as m
+    m.load()
+    return m
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(emt_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function(emt):
+    names = declared_functions()
+    assert set(names) == set(emt.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", emt.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (emt_[a-z_]+)", out))
+    for n in names:
+        assert n in exported, n
+        assert hasattr(emt.load(), n)
+
+
+def test_struct_layout_matches_header(emt):
+    prog = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "emt.h"
+#define S(t) printf(#t " %zu\n", sizeof(t));
+#define O(t, f) printf(#t "." #f " %zu\n", offsetof(t, f));
+int main(void) {
+  S(emt_config) S(emt_view_in) S(emt_track) S(emt_view_stats) S(emt_view_out) S(emt_call_stats)
+  O(emt_config, hbm_budget) O(emt_config, stream) O(emt_track, slope) O(emt_track, t_end)
+  O(emt_view_out, tracks) O(emt_view_out, stats) O(emt_call_stats, ms) O(emt_call_stats, ms_total)
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "l.c")
+        exe = os.path.join(d, "l")
+        open(src, "w").write(prog)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        lines = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(line.rsplit(" ", 1) for line in lines if line)
+    exp = {
+        "emt_config": C.sizeof(emt.EmtConfig), "emt_view_in": C.sizeof(emt.EmtViewIn),
+        "emt_track": C.sizeof(emt.EmtTrack), "emt_view_stats": C.sizeof(emt.EmtViewStats),
+        "emt_view_out": C.sizeof(emt.EmtViewOut), "emt_call_stats": C.sizeof(emt.EmtCallStats),
+        "emt_config.hbm_budget": emt.EmtConfig.hbm_budget.offset,
+        "emt_config.stream": emt.EmtConfig.stream.offset,
+        "emt_track.slope": emt.EmtTrack.slope.offset,
+        "emt_track.t_end": emt.EmtTrack.t_end.offset,
+        "emt_view_out.tracks": emt.EmtViewOut.tracks.offset,
+        "emt_view_out.stats": emt.EmtViewOut.stats.offset,
+        "emt_call_stats.ms": emt.EmtCallStats.ms.offset,
+        "emt_call_stats.ms_total": emt.EmtCallStats.ms_total.offset,
+    }
+    for k, v in exp.items():
+        assert int(got[k]) == v, (k, got[k], v)
+    assert emt.TRACK_DTYPE.itemsize == C.sizeof(emt.EmtTrack)
+
+
+def test_defaults_and_strerror(emt):
+    cfg = emt.emt_default_config()
+    assert cfg.abi_version == emt.EMT_ABI_VERSION
+    assert (cfg.seed_dist, cfg.tol_radius, cfg.min_grains) == (2500, 50, 8)
+    for rc in (0, -1, -2, -3, -4, -5):
+        assert emt.emt_strerror(rc)
+    assert emt.emt_strerror(12345) == "unknown error"
+
+
+@pytest.mark.parametrize("field,value,rc", [
+    ("abi_version", 7, -1), ("flags", 0x100, -1), ("cell_xy", -5, -1), ("device", -1, -1),
+    ("seed_dist", 0, -2), ("seed_dist", 4097, -2), ("tol_radius", -1, -2),
+    ("tol_radius", 2500, -2), ("min_grains", 1, -2), ("min_grains", 1 << 20, -2),
+    ("cell_z", (1 << 18) + 1, -2),
+])
+def test_validate_rejects_bad_config(emt, field, value, rc):
+    cfg = emt.emt_default_config()
+    setattr(cfg, field, value)
+    assert emt.emt_validate(cfg) == rc
+
+
+def test_validate_views(emt):
+    cfg = emt.emt_default_config()
+    ok = np.array([[0, 0, 0], [100, 200, 300]], np.int32)
+    assert emt.emt_validate(cfg, [ok, np.zeros((0, 3), np.int32)]) == 0
+    wide = np.array([[0, 0, 0], [(1 << 18) + 1, 0, 0]], np.int32)
+    assert emt.emt_validate(cfg, [ok, wide]) == -2
+    edge = np.array([[0, 0, 0], [0, 0, 1 << 18]], np.int32)
+    assert emt.emt_validate(cfg, [edge]) == 0
+    neg = np.array([[-(1 << 17), 0, 0], [(1 << 17) + 1, 0, 0]], np.int32)
+    assert emt.emt_validate(cfg, [neg]) == -2
+
+
+def test_validate_null_and_count(emt):
+    lib = emt.load()
+    cfg = emt.emt_default_config()
+    assert lib.emt_validate(None, None, 0) == -1
+    assert lib.emt_validate(C.byref(cfg), None, 1) == -1
+    v = (emt.EmtViewIn * 1)()
+    v[0].xyz = None
+    v[0].n_grains = 5
+    assert lib.emt_validate(C.byref(cfg), v, 1) == -1
+    v[0].n_grains = 1 << 20
+    v[0].xyz = 8  # never read: the count is rejected first
+    assert lib.emt_validate(C.byref(cfg), v, 1) == -2
+
+
+def test_create_and_track_reject_null_without_device(emt):
+    lib = emt.load()
+    assert lib.emt_create(None, None) == -1
+    h = C.c_void_p()
+    bad = emt.emt_default_config(abi_version=3)
+    assert lib.emt_create(C.byref(bad), C.byref(h)) == -1
+    assert h.value is None
+    assert lib.emt_track_views(None, None, 0, None) == -1
+    assert lib.emt_last_stats(None, None) == -1
+    lib.emt_destroy(None)

@@ -1,0 +1,215 @@
+"""GPU library vs CPU oracle, through the C ABI, on seeded synthetic views.
+
+Track lists (seed pairs, order, grain lists, grain order) must be identical;
+fitted quantities within the tolerances stated in tests/parity.py.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1311_5334_amd import synth
+from parity import assert_view_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def emt():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1311_5334_amd import emt as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def tracker(emt):
+    t = emt.Tracker(device=0, flags=emt.EMT_F_STATS)
+    yield t
+    t.close()
+
+
+def run1(tracker, xyz):
+    return tracker([xyz])[0]
+
+
+@pytest.mark.parametrize("index", range(6))
+def test_config1_views(tracker, oracle_mod, index):
+    v = synth.make_c1(index)
+    _say(f"c1 view {index}: {v.n} grains")
+    assert_view_parity(v.xyz, run1(tracker, v.xyz), oracle_mod.track_view(v.xyz))
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_tiny_dense_views(emt, oracle_mod, seed):
+    rng = np.random.default_rng(seed)
+    kind = seed % 3
+    if kind == 0:
+        v = synth.make_tiny_tracks(1000 + seed, int(rng.integers(2, 6)),
+                                   int(rng.integers(20, 120)), 30.0,
+                                   float(rng.uniform(0.6, 1.5)))
+        n_min = 8
+    elif kind == 1:
+        v = synth.make_box_view(2000 + seed, int(rng.integers(20, 200)), (15.0, 15.0, 15.0))
+        n_min = 4
+    else:
+        pts = rng.integers(0, 6, size=(int(rng.integers(30, 150)), 3)) * 300
+        v = synth.View(pts.astype(np.int32), np.full(len(pts), -1, np.int32), (18, 18))
+        n_min = 5
+    with emt.Tracker(device=0, min_grains=n_min) as t:
+        got = run1(t, v.xyz)
+    assert_view_parity(v.xyz, got, oracle_mod.track_view(v.xyz, n_min=n_min))
+
+
+@pytest.mark.parametrize("index", range(2))
+def test_config2_full_views(tracker, oracle_mod, index):
+    v = synth.make_c2(index)
+    _say(f"c2 view {index}: {v.n} grains")
+    got = run1(tracker, v.xyz)
+    st = tracker.stats()
+    assert st["retries"] == 0 or index == 0
+    assert_view_parity(v.xyz, got, oracle_mod.track_view(v.xyz))
+
+
+def test_edge_cases(emt, oracle_mod):
+    cases = [
+        np.zeros((0, 3), np.int32),
+        np.array([[5, 6, 7]], np.int32),
+        np.array([[0, 0, 0], [100, 0, 0]], np.int32),
+        np.array([[5, 5, 5]] * 20, np.int32),
+        np.array([[20000 + 300 * m, 30000 - 200 * m, 100 * m] for m in range(12)], np.int32),
+        np.array([[-(1 << 17), 0, 0], [(1 << 17) - 1, 0, 0], [0, 5, 5]], np.int32),
+    ]
+    with emt.Tracker(device=0) as t:
+        for xyz in cases:
+            assert_view_parity(xyz, run1(t, xyz), oracle_mod.track_view(xyz))
+        # all of them in one batch
+        res = t(cases)
+        for xyz, got in zip(cases, res):
+            assert_view_parity(xyz, got, oracle_mod.track_view(xyz))
+
+
+def test_span_limit_is_an_error(emt):
+    wide = np.array([[0, 0, 0], [(1 << 18) + 1, 0, 0]], np.int32)
+    with emt.Tracker(device=0) as t:
+        with pytest.raises(emt.EmtError) as e:
+            t([wide])
+        assert e.value.rc == emt.EMT_ERANGE
+
+
+def test_span_limit_device_pointers(emt):
+    import torch
+    wide = torch.tensor([[0, 0, 0], [(1 << 18) + 1, 0, 0]], dtype=torch.int32, device="cuda:0")
+    with emt.Tracker(device=0, flags=emt.EMT_F_DEVICE_PTRS) as t:
+        with pytest.raises(emt.EmtError) as e:
+            t([wide])
+        assert e.value.rc == emt.EMT_ERANGE
+
+
+def test_boundary_cases_counted_exactly(emt, oracle_mod):
+    import json
+    from test_oracle import signed_perms
+    here = os.path.dirname(os.path.abspath(__file__))
+    cases = json.load(open(os.path.join(here, "golden", "boundary_cases.json")))["cases"]
+    base = np.array([100000, 100000, 100000], np.int64)
+    with emt.Tracker(device=0, min_grains=2) as t2, emt.Tracker(device=0, min_grains=3) as t3:
+        for case in cases:
+            for M in signed_perms():
+                xyz = np.array([base + M @ np.array(p, np.int64) for p in case["points"]],
+                               np.int64).astype(np.int32)
+                if case["kind"] == "seed":
+                    got = run1(t2, xyz)
+                    assert got["n_seeds"] == case["expect_seeds"], case["name"]
+                else:
+                    got = run1(t3, xyz)
+                    ref = oracle_mod.track_view(xyz, n_min=3)
+                    assert_view_parity(xyz, got, ref)
+                    has = any(int(tr["seed"][0]) == 0 and int(tr["seed"][1]) == 1
+                              for tr in got["tracks"])
+                    if case["expect_count"] == 3:
+                        assert got["n_candidates"] >= 1
+                    else:
+                        assert not has
+
+
+def test_device_pointers_match_host(emt, tracker):
+    import torch
+    v = synth.make_c1(9)
+    host = run1(tracker, v.xyz)
+    with emt.Tracker(device=0, flags=emt.EMT_F_DEVICE_PTRS) as t:
+        dev = t([torch.from_numpy(v.xyz).to("cuda:0")])[0]
+    assert host["tracks"].tobytes() == dev["tracks"].tobytes()
+    assert np.array_equal(host["grains"], dev["grains"])
+
+
+def test_repeat_is_byte_identical(tracker):
+    v = synth.make_c1(11)
+    first = run1(tracker, v.xyz)
+    for _ in range(5):
+        again = run1(tracker, v.xyz)
+        assert again["tracks"].tobytes() == first["tracks"].tobytes()
+        assert np.array_equal(again["grains"], first["grains"])
+
+
+def test_batch_equals_views_alone(tracker, oracle_mod):
+    views = [synth.make_c1(i).xyz for i in range(12, 16)] + [synth.make_c4(i).xyz for i in range(3)]
+    views = [x for x in views if len(x) < 8000] + [np.zeros((0, 3), np.int32)]
+    alone = [run1(tracker, x) for x in views]
+    batch = tracker(views)
+    for a, b in zip(alone, batch):
+        assert a["tracks"].tobytes() == b["tracks"].tobytes()
+        assert np.array_equal(a["grains"], b["grains"])
+    for x, b in zip(views[:4], batch[:4]):
+        assert_view_parity(x, b, oracle_mod.track_view(x))
+
+
+def test_overflow_retry_gives_same_result(emt, tracker, monkeypatch):
+    v = synth.make_c1(17)
+    ref = run1(tracker, v.xyz)
+    monkeypatch.setenv("EMT_INITIAL_CAPS", "tiny")
+    with emt.Tracker(device=0) as t:
+        got = run1(t, v.xyz)
+        assert t.stats()["retries"] >= 1
+    assert got["tracks"].tobytes() == ref["tracks"].tobytes()
+    assert np.array_equal(got["grains"], ref["grains"])
+
+
+def test_cell_geometry_never_changes_results(emt, oracle_mod):
+    v = synth.make_c1(18)
+    ref = oracle_mod.track_view(v.xyz)
+    for cxy, cz in ((150, 170), (500, 500), (1200, 300), (3000, 5000), (97, 61)):
+        with emt.Tracker(device=0, cell_xy=cxy, cell_z=cz) as t:
+            assert_view_parity(v.xyz, run1(t, v.xyz), ref)
+
+
+def test_axis_permutations_on_gpu(tracker, oracle_mod):
+    from test_oracle import signed_perms
+    v = synth.make_c1(19)
+    ref = oracle_mod.track_view(v.xyz)
+    for M in list(signed_perms())[::5]:
+        xyz = (v.xyz.astype(np.int64) @ M.T).astype(np.int32)
+        got = run1(tracker, xyz)
+        assert len(got["tracks"]) == len(ref.tracks)
+        for k in range(len(ref.tracks)):
+            g = got["tracks"][k]
+            off = int(g["grain_offset"])
+            assert np.array_equal(got["grains"][off:off + int(g["n_grains"])],
+                                  ref.track_grains(k))
+
+
+def test_fp64_always_flag(emt, oracle_mod):
+    v = synth.make_c1(20)
+    ref = oracle_mod.track_view(v.xyz)
+    with emt.Tracker(device=0, flags=emt.EMT_F_FP64_FIT_ALWAYS) as t:
+        got = run1(t, v.xyz)
+    assert np.all(got["tracks"]["fit_fp64"] == 1)
+    for k, rt in enumerate(ref.tracks):
+        for s in range(2):
+            assert abs(np.arctan(got["tracks"][k]["slope"][s]) - np.arctan(rt["slope"][s])) < 1e-6
