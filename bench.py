@@ -1,0 +1,149 @@
+"""Throughput of the 4pi track finder on one MI355X.
+
+One step = one whole pass of the tracking path (bin, seeds, count, members,
+merge, fit, copy-out) over one full view of the c2 workload: 350 x 350 x 50
+um, 300 isotropic tracks (20 % stopping), fog 3 grains per 1000 um^3, about
+27.6k grains. The grains are resident in HBM before the timed region starts
+(device-pointer input); results are copied back to the host inside it.
+
+Prints one JSON line: grains/s (value), mm^2/hour, view latency p50/p99, the
+counting kernel's roofline (HIP events on the library's stream), and the
+CPU oracle timed on one view on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# VALU peak for 32-bit lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# Algorithmic operations per (seed, grain) cylinder test: cross product
+# g_k x d - g_i x d (6 multiplies, 6 subtractions), squared norm (3
+# multiplies, 2 adds), one compare.
+OPS_PER_TEST = 18
+HBM_PEAK_GBS = 8000.0
+COUNT_KERNEL_SRC = os.path.join(ROOT, "paper_1311_5334_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "count_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(open(COUNT_KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_for_current_kernel(per_launch_tests: float):
+    """HBM bytes per launch of the counting kernel from the committed PMC
+    summary, only if it was taken on the current kernel source."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(view, max_seconds: float = 30.0):
+    from oracle import oracle
+    oracle.build()
+    t0 = time.perf_counter()
+    oracle.track_view(view.xyz)
+    dt = time.perf_counter() - t0
+    return {"value": view.n / dt, "unit": "grains/s", "cores": 1, "kind": "oracle",
+            "sample": f"one c2 view ({view.n} grains), single-threaded C oracle, "
+                      f"{dt:.2f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--view-index", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); views are "
+              "independent, so N GPUs would each run this same per-GPU workload", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1311_5334_amd import emt, synth
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    view = synth.make_c2(args.view_index)
+    dev = torch.from_numpy(view.xyz).to("cuda:0").contiguous()
+    torch.cuda.synchronize()
+    tr = emt.Tracker(device=0, flags=emt.EMT_F_DEVICE_PTRS | emt.EMT_F_STATS)
+    for _ in range(args.warmup):
+        tr([dev])
+    torch.cuda.synchronize()
+
+    lat, stage_ms = [], []
+    stats = None
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        res = tr([dev])
+        lat.append(time.perf_counter() - t0)
+        st = tr.stats()
+        stage_ms.append(st["ms"])
+        stats = st
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    tr.close()
+
+    grains = view.n * args.steps
+    value = grains / wall
+    mm2_h = view.area_mm2 * args.steps / wall * 3600.0
+    lat_ms = np.array(lat) * 1e3
+    ms = {k: float(np.mean([s[k] for s in stage_ms])) for k in stage_ms[0]}
+    count_s = ms["count"] * 1e-3
+    tests = stats["n_tests"]
+    achieved = tests * OPS_PER_TEST / count_s / 1e12
+    peak = VALU_PEAK_OPS / 1e12
+    out = {
+        "metric": "grains/s and mm^2/hour per GPU (plain per-view path); p50/p99 view latency",
+        "value": round(value, 1),
+        "unit": "grains/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32",
+        "data": "synthetic",
+        "config": {"workload": "c2: one full 350x350x50 um view, 300 tracks, "
+                               "fog 3/1000 um^3, R=25 um, r=0.5 um, n_min=8",
+                   "grains_per_view": view.n, "form": "plain", "views_per_step": 1},
+        "mm2_per_hour": round(mm2_h, 2),
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 4)},
+        "stage_ms": {k: round(v, 4) for k, v in ms.items()},
+        "work": {"seeds": stats["n_seeds"], "tests": tests, "hits": stats["n_hits"],
+                 "tests_per_hit": round(tests / max(1, stats["n_hits"]), 3),
+                 "candidates": stats["n_candidates"], "tracks": stats["n_tracks"],
+                 "merge_rounds": stats["merge_rounds"], "fp64_fits": stats["n_fp64_fits"]},
+        "roofline": {"kernel": "k_count", "bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(peak, 2), "unit": "Tops/s",
+                     "frac": round(achieved / peak, 4),
+                     "traffic": traffic_for_current_kernel(tests)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(view)
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -26,6 +26,8 @@ constexpr int kDefaultCellXY = 750;  // 7.5 um, the paper's 32-pixel hash cell
 constexpr int kDefaultCellZ = 500;
 constexpr int kMaxAttempts = 4;
 constexpr int kRoundChunk = 8;
+// seeds of one call are indexed by uint32 and scanned in uint32
+constexpr unsigned long long kSeedCapMax = (1ull << 31) - 1;
 
 struct DevArena {
     void *p = nullptr;
@@ -176,22 +178,30 @@ int ensure(emt_ctx *ctx, Caps &c) {
     DevPtrs &d = ctx->d;
     if (c.n_total > ctx->cap_n || !ctx->grain_buf.p) {
         const size_t n = std::max<uint32_t>(c.n_total, 1024);
-        const size_t b = bytes_of<int32_t>(3 * n) + 3 * bytes_of<uint32_t>(n) + bytes_of<int4>(n) +
-                         bytes_of<uint8_t>(n) + bytes_of<unsigned long long>(n);
+        const size_t b = bytes_of<int32_t>(3 * n) + 4 * bytes_of<uint32_t>(n) +
+                         bytes_of<uint32_t>(n + 1) + bytes_of<int4>(n) + bytes_of<uint8_t>(n) +
+                         bytes_of<unsigned long long>(n);
         if ((rc = arena(ctx, ctx->grain_buf, b))) return rc;
         char *p = (char *)ctx->grain_buf.p;
         d.xyz = carve<int32_t>(p, 3 * n);
         d.view_of = carve<uint32_t>(p, n);
         d.cell_of = carve<uint32_t>(p, n);
         d.rank = carve<uint32_t>(p, n);
+        d.seed_cnt = carve<uint32_t>(p, n);
+        d.seed_off = carve<uint32_t>(p, n + 1);
         d.sg = carve<int4>(p, n);
         d.used = carve<uint8_t>(p, n);
         d.owner = carve<unsigned long long>(p, n);
         ctx->cap_n = (uint32_t)n;
     }
     if (c.seed_cap > ctx->cap_seeds || !ctx->seed_buf.p) {
-        if ((rc = arena(ctx, ctx->seed_buf, bytes_of<uint2>(c.seed_cap)))) return rc;
-        d.seeds = (uint2 *)ctx->seed_buf.p;
+        const size_t n = c.seed_cap;
+        const size_t b = bytes_of<uint2>(n) + bytes_of<uint32_t>(n) + bytes_of<uint32_t>(n + 1);
+        if ((rc = arena(ctx, ctx->seed_buf, b))) return rc;
+        char *p = (char *)ctx->seed_buf.p;
+        d.seeds = carve<uint2>(p, n);
+        d.seed_n = carve<uint32_t>(p, n);
+        d.cand_pos = carve<uint32_t>(p, n + 1);
         ctx->cap_seeds = c.seed_cap;
     }
     if (c.cand_cap > ctx->cap_cand || !ctx->cand_buf.p) {
@@ -232,8 +242,11 @@ int ensure(emt_ctx *ctx, Caps &c) {
     c.seed_cap = std::max<unsigned long long>(c.seed_cap, ctx->cap_seeds);
     c.cand_cap = std::max(c.cand_cap, ctx->cap_cand);
     c.mem_cap = std::max(c.mem_cap, ctx->cap_mem);
-    const uint32_t scan_cap = std::max<uint32_t>(c.n_cells, c.cand_cap) + 1;
-    if (c.n_cells > ctx->cap_cells || c.cand_cap + 1 > ctx->cap_cells || !ctx->cell_buf.p) {
+    // the scan scratch serves every scan: cells, anchors, seeds, candidates
+    const uint32_t scan_cap =
+        std::max<uint32_t>(std::max<uint32_t>(c.n_cells, c.cand_cap),
+                           std::max<uint32_t>((uint32_t)c.seed_cap, c.n_total)) + 1;
+    if (scan_cap > ctx->cap_cells || !ctx->cell_buf.p) {
         const size_t n = std::max<uint32_t>(scan_cap, 1u << 16);
         const size_t b = 2 * bytes_of<uint32_t>(n) + bytes_of<uint32_t>(scan_scratch_words((uint32_t)n));
         if ((rc = arena(ctx, ctx->cell_buf, b))) return rc;
@@ -328,6 +341,7 @@ int run_once(emt_ctx *ctx, const emt_view_in *views, uint32_t nv, const Caps &c,
     record(ctx, 3);
     launch_count(run, c, ctx->P, s);
     record(ctx, 4);
+    launch_candidates(run, c, ctx->P, s);
     launch_members(run, c, ctx->P, s);
     record(ctx, 5);
     launch_merge_init(run, c, ctx->P, s);
@@ -493,8 +507,9 @@ int emt_track_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views, em
     c.n_total = (uint32_t)n_total;
     c.n_cells = (uint32_t)n_cells;
     c.max_view_n = max_n;
-    c.seed_cap = std::max<unsigned long long>(
-        4096, (unsigned long long)(ctx->seeds_per_grain * (double)n_total));
+    c.seed_cap = std::min<unsigned long long>(
+        kSeedCapMax, std::max<unsigned long long>(
+                         4096, (unsigned long long)(ctx->seeds_per_grain * (double)n_total)));
     c.cand_cap = clamp_u32(ctx->cand_per_grain * (double)n_total);
     c.mem_cap = clamp_u32(ctx->mem_per_cand * (double)c.cand_cap);
 
@@ -543,7 +558,9 @@ int emt_track_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views, em
         // the counters are exact for the stage that overflowed; later stages
         // are sized from the per-grain and per-candidate ratios
         if (h.n_seeds > c.seed_cap) {
-            c.seed_cap = h.n_seeds + h.n_seeds / 8 + 1024;
+            if (h.n_seeds >= kSeedCapMax) return EMT_EOVERFLOW;
+            c.seed_cap = std::min<unsigned long long>(kSeedCapMax,
+                                                      h.n_seeds + h.n_seeds / 8 + 1024);
             ctx->seeds_per_grain = std::max(ctx->seeds_per_grain, 1.125 * (double)h.n_seeds / std::max(1.0, (double)n_total));
         }
         if (h.n_cand > c.cand_cap) {

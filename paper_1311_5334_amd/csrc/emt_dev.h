@@ -40,7 +40,8 @@ struct Params {
 // Device counters of one call. Totals keep counting past capacities so the
 // host learns what a retry needs.
 struct Counters {
-    unsigned long long n_seeds;
+    uint32_t n_seeds;
+    uint32_t pad0;
     unsigned long long tests;
     unsigned long long hits;
     uint32_t n_cand;
@@ -80,7 +81,11 @@ struct DevPtrs {
     uint32_t *cell_count; // C
     uint32_t *cell_start; // C
     int4 *sg;             // N sorted grains: x, y, z relative to lo; w = input index
+    uint32_t *seed_cnt;   // N: seeds per anchor
+    uint32_t *seed_off;   // N + 1
     uint2 *seeds;         // seed_cap
+    uint32_t *seed_n;     // seed_cap: count if >= n_min, else 0
+    uint32_t *cand_pos;   // seed_cap + 1
     Cand *cand;           // cand_cap
     unsigned long long *key;  // cand_cap
     uint32_t *cand_n;     // cand_cap + 1
@@ -125,6 +130,7 @@ void launch_prepare(const DevPtrs &d, const Caps &c, const Params &P, hipStream_
 void launch_bin(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
 void launch_seeds(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
 void launch_count(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
+void launch_candidates(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
 void launch_members(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
 void launch_merge_init(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
 void launch_merge_round(const DevPtrs &d, const Caps &c, const Params &P, int round,

@@ -108,13 +108,20 @@ __device__ __forceinline__ uint32_t scan_len(const uint32_t *n_dev, uint32_t n_c
     return n < n_cap ? n : n_cap;
 }
 
+template <bool kFlag>
+__device__ __forceinline__ uint32_t scan_in(const uint32_t *in, uint32_t i) {
+    const uint32_t v = in[i];
+    return kFlag ? (v != 0u ? 1u : 0u) : v;
+}
+
+template <bool kFlag>
 __global__ void __launch_bounds__(kBlock) k_scan_part(const uint32_t *in, const uint32_t *n_dev,
                                                       uint32_t n_cap, uint32_t *part) {
     const uint32_t n = scan_len(n_dev, n_cap);
     const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
     uint32_t s = 0;
     for (int i = 0; i < kScanItems; ++i)
-        if (base + i < n) s += in[base + i];
+        if (base + i < n) s += scan_in<kFlag>(in, base + i);
     uint32_t tot;
     block_excl_scan(s, &tot);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
@@ -141,6 +148,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_part_scan(uint32_t *part, uint3
     }
 }
 
+template <bool kFlag>
 __global__ void __launch_bounds__(kBlock) k_scan_apply(const uint32_t *in, const uint32_t *n_dev,
                                                        uint32_t n_cap, const uint32_t *part,
                                                        uint32_t *out) {
@@ -150,7 +158,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const uint32_t *in, const
     uint32_t v[kScanItems];
     uint32_t s = 0;
     for (int i = 0; i < kScanItems; ++i) {
-        v[i] = (base + i < n) ? in[base + i] : 0u;
+        v[i] = (base + i < n) ? scan_in<kFlag>(in, base + i) : 0u;
         s += v[i];
     }
     uint32_t tot;
@@ -162,13 +170,14 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const uint32_t *in, const
 }
 
 // out[i] = sum of in[0..i) for i <= n, n = min(*n_dev, n_cap) (n_cap if no
-// n_dev); *total_out = out[n].
+// n_dev); *total_out = out[n]. With kFlag the summands are (in[i] != 0).
+template <bool kFlag = false>
 void scan_excl(const uint32_t *in, const uint32_t *n_dev, uint32_t n_cap, uint32_t *part,
                uint32_t *out, uint32_t *total_out, hipStream_t s) {
     const uint32_t nb = n_cap / kScanTile + 1;
-    k_scan_part<<<nb, kBlock, 0, s>>>(in, n_dev, n_cap, part);
+    k_scan_part<kFlag><<<nb, kBlock, 0, s>>>(in, n_dev, n_cap, part);
     k_scan_part_scan<<<1, kBlock, 0, s>>>(part, nb, n_dev, n_cap, out, total_out);
-    k_scan_apply<<<nb, kBlock, 0, s>>>(in, n_dev, n_cap, part, out);
+    k_scan_apply<kFlag><<<nb, kBlock, 0, s>>>(in, n_dev, n_cap, part, out);
 }
 
 // ------------------------------------------------------------------- bin
@@ -298,107 +307,150 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const int32_t *xyz, const Vi
 }
 
 // ------------------------------------------------------------ line walk
-
-// Visit every grain that can lie within r of the infinite line through g
-// with direction d (any view grain closer than r is visited; the caller's
-// exact predicate decides).
 //
-// With a the axis of largest |d_a| and b, c the others: a grain k in the cell
-// layers [A0, A1] along a and within r of the line satisfies
-// |k_b - p_b(k_a)| <= r|d|/|d_a| (p = line point with the same a), because
-// for v = k - p(k_a), v_a = 0 and |v x d| >= |v| |d_a|. p_b is linear in a,
-// so the b range of the layer is [min(p_b(A0), p_b(A1)) - rho,
-// max(...) + rho]; same for c. Cells along x are contiguous in memory, so each
-// (y, z) row of the window is one run of grains.
-template <class F>
-__device__ __forceinline__ void walk_line(const int4 *__restrict__ sg,
-                                          const uint32_t *__restrict__ cs,
-                                          const ViewGrid *__restrict__ Gp, int slab_x, int gx,
-                                          int gy, int gz, int dx, int dy, int dz, int r, F &on) {
-    const int nx = Gp->dims[0], ny = Gp->dims[1], nz = Gp->dims[2];
-    const int cx = Gp->cell[0], cy = Gp->cell[1], cz = Gp->cell[2];
-    const uint32_t off = Gp->cell_off;
-    const int adx = abs(dx), ady = abs(dy), adz = abs(dz);
-    const int a = (adx >= ady && adx >= adz) ? 0 : (ady >= adz ? 1 : 2);
-    const int ga = a == 0 ? gx : (a == 1 ? gy : gz);
-    const int gb = a == 0 ? gy : gx;
-    const int gc = a == 2 ? gy : gz;
-    const int da = a == 0 ? dx : (a == 1 ? dy : dz);
-    const int db = a == 0 ? dy : dx;
-    const int dc = a == 2 ? dy : dz;
-    const int ca = a == 0 ? cx : (a == 1 ? cy : cz);
-    const int cb = a == 0 ? cy : cx;
-    const int cc = a == 2 ? cy : cz;
-    const int na = a == 0 ? nx : (a == 1 ? ny : nz);
-    const int nb = a == 0 ? ny : nx;
-    const int nc = a == 2 ? ny : nz;
-    const float inv = 1.0f / (float)da;
-    const float sb = (float)db * inv, sc = (float)dc * inv;
-    const float rho = (float)r * sqrtf((float)(dx * dx + dy * dy + dz * dz)) * fabsf(inv) + kMargin;
-    const float ica = 1.0f / (float)ca, icb = 1.0f / (float)cb, icc = 1.0f / (float)cc;
+// Which cells can hold a grain within r of the infinite line p(t) = g + t d?
+// If |k - p(t*)| <= r then |k_m - p_m(t*)| <= r on every axis. Cells along x
+// are contiguous in memory, so the walk enumerates (y, z) pencils: for each
+// (y, z) cell that the projected line, widened by r on each axis, crosses,
+// it takes the parameter interval during which p_y and p_z stay within r of
+// that cell, and the x range p_x covers on it, widened by r. That x range is
+// one contiguous run of sorted grains. The traversal steps along the larger
+// of |d_y|, |d_z| (axis e), and for each e cell across the f cells the line
+// can reach. FP32 values only choose cells: every bound is widened by
+// kMargin units, more than the rounding of any coordinate below 2^20, and
+// the exact integer predicate decides each grain.
+struct Run {
+    uint32_t k, e;
+};
 
-    // Layers along a where the widened line meets the grid in b and c.
-    float alo = 0.0f, ahi = (float)(na * ca - 1);
-    if (db != 0) {
-        const float t1 = (float)ga + (-rho - (float)gb) / sb;
-        const float t2 = (float)ga + ((float)(nb * cb - 1) + rho - (float)gb) / sb;
-        alo = fmaxf(alo, fminf(t1, t2));
-        ahi = fminf(ahi, fmaxf(t1, t2));
-    }
-    if (dc != 0) {
-        const float t1 = (float)ga + (-rho - (float)gc) / sc;
-        const float t2 = (float)ga + ((float)(nc * cc - 1) + rho - (float)gc) / sc;
-        alo = fmaxf(alo, fminf(t1, t2));
-        ahi = fminf(ahi, fmaxf(t1, t2));
-    }
-    const int ia0 = (int)floorf(fminf(fmaxf(alo * ica - 1.0f, 0.0f), (float)na));
-    const int ia1 = (int)floorf(fmaxf(fminf(ahi * ica + 1.0f, (float)(na - 1)), -1.0f));
-    const int T = a == 0 ? slab_x : 1;
+struct Pencil {
+    float gx, dx, ge, de, gf, df, inv_de, inv_df;
+    float rr, tlo, thi, icx, ce, cf;
+    int nx, ny, nf;
+    uint32_t off;
+    bool e_is_y;
+    int ie, ie1, jf, jf1;
+    float ta, tb;
+    bool live;
 
-    for (int ia = ia0; ia <= ia1; ia += T) {
-        const int ie = min(ia + T - 1, na - 1);
-        const float u0 = (float)(ia * ca - ga);
-        const float u1 = (float)((ie + 1) * ca - 1 - ga);
-        const float pb0 = (float)gb + u0 * sb, pb1 = (float)gb + u1 * sb;
-        const float pc0 = (float)gc + u0 * sc, pc1 = (float)gc + u1 * sc;
-        const int ib0 = max(0, (int)floorf(fmaxf((fminf(pb0, pb1) - rho) * icb, -1.0f)));
-        const int ib1 = min(nb - 1, (int)floorf(fminf((fmaxf(pb0, pb1) + rho) * icb, (float)nb)));
-        const int ic0 = max(0, (int)floorf(fmaxf((fminf(pc0, pc1) - rho) * icc, -1.0f)));
-        const int ic1 = min(nc - 1, (int)floorf(fminf((fmaxf(pc0, pc1) + rho) * icc, (float)nc)));
-        if (ib0 > ib1 || ic0 > ic1) continue;
-        const int x0 = a == 0 ? ia : ib0;
-        const int x1 = a == 0 ? ie : ib1;
-        const int y0 = a == 1 ? ia : (a == 0 ? ib0 : ic0);
-        const int y1 = a == 1 ? ia : (a == 0 ? ib1 : ic1);
-        const int z0 = a == 2 ? ia : ic0;
-        const int z1 = a == 2 ? ia : ic1;
-        for (int z = z0; z <= z1; ++z) {
-            for (int y = y0; y <= y1; ++y) {
-                const uint32_t row = off + (uint32_t)((z * ny + y) * nx);
-                const uint32_t k0 = cs[row + x0], k1 = cs[row + x1 + 1];
-                for (uint32_t k = k0; k < k1; ++k) on(k, sg[k]);
+    __device__ __forceinline__ void init(const ViewGrid *__restrict__ Gp, int4 g, int idx, int idy,
+                                         int idz, int r, bool valid) {
+        nx = Gp->dims[0];
+        ny = Gp->dims[1];
+        const int nz = Gp->dims[2];
+        const float cx = (float)Gp->cell[0], cy = (float)Gp->cell[1], cz = (float)Gp->cell[2];
+        off = Gp->cell_off;
+        rr = (float)r + kMargin;
+        icx = 1.0f / cx;
+        gx = (float)g.x;
+        dx = (float)idx;
+        const float gy = (float)g.y, gz = (float)g.z, dy = (float)idy, dz = (float)idz;
+        // parameter range in which the line is within rr of the grid box
+        tlo = -3.0e38f;
+        thi = 3.0e38f;
+        const float gm[3] = {gx, gy, gz}, dm[3] = {dx, dy, dz};
+        const float hm[3] = {(float)(nx * Gp->cell[0] - 1), (float)(ny * Gp->cell[1] - 1),
+                             (float)(nz * Gp->cell[2] - 1)};
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            if (dm[m] != 0.0f) {
+                const float t1 = (-rr - gm[m]) / dm[m];
+                const float t2 = (hm[m] + rr - gm[m]) / dm[m];
+                tlo = fmaxf(tlo, fminf(t1, t2));
+                thi = fminf(thi, fmaxf(t1, t2));
             }
         }
+        e_is_y = fabsf(dy) >= fabsf(dz);
+        ge = e_is_y ? gy : gz;
+        de = e_is_y ? dy : dz;
+        gf = e_is_y ? gz : gy;
+        df = e_is_y ? dz : dy;
+        ce = e_is_y ? cy : cz;
+        cf = e_is_y ? cz : cy;
+        const int ne = e_is_y ? ny : nz;
+        nf = e_is_y ? nz : ny;
+        inv_de = de != 0.0f ? 1.0f / de : 0.0f;
+        inv_df = df != 0.0f ? 1.0f / df : 0.0f;
+        // e cells the widened projection touches
+        const float ea = ge + tlo * de, eb = ge + thi * de;
+        const float elo = (de != 0.0f ? fminf(ea, eb) : ge) - rr;
+        const float ehi = (de != 0.0f ? fmaxf(ea, eb) : ge) + rr;
+        const int ie0 = max(0, (int)floorf(fmaxf(elo / ce, -1.0f)));
+        ie1 = min(ne - 1, (int)floorf(fminf(ehi / ce, (float)ne)));
+        ie = ie0 - 1;
+        jf = 1;
+        jf1 = 0;
+        ta = tb = 0.0f;
+        live = valid && ie0 <= ie1 && tlo <= thi;
     }
-}
+
+    // Parameter interval and f cells of e cell ie.
+    __device__ __forceinline__ void setup_e() {
+        const float E0 = (float)ie * ce - rr, E1 = (float)(ie + 1) * ce - 1.0f + rr;
+        if (de != 0.0f) {
+            const float t1 = (E0 - ge) * inv_de, t2 = (E1 - ge) * inv_de;
+            ta = fmaxf(tlo, fminf(t1, t2));
+            tb = fminf(thi, fmaxf(t1, t2));
+        } else {
+            ta = tlo;
+            tb = (ge >= E0 && ge <= E1) ? thi : tlo - 1.0f;
+        }
+        if (ta > tb) {
+            jf = 1;
+            jf1 = 0;
+            return;
+        }
+        const float fa = gf + ta * df, fb = gf + tb * df;
+        jf = max(0, (int)floorf(fmaxf((fminf(fa, fb) - rr) / cf, -1.0f)));
+        jf1 = min(nf - 1, (int)floorf(fminf((fmaxf(fa, fb) + rr) / cf, (float)nf)));
+    }
+
+    // One move of the walk: the next f cell of the current e cell (or the
+    // set-up of the next e cell). Fills out with that pencil's run, or an
+    // empty run; the two cell_start loads are issued but not waited on.
+    __device__ __forceinline__ void fetch(const uint32_t *__restrict__ cs, Run &out) {
+        out.k = out.e = 0;
+        if (!live) return;
+        if (jf > jf1) {
+            if (++ie > ie1) {
+                live = false;
+                return;
+            }
+            setup_e();
+            if (jf > jf1) return;
+        }
+        const int j = jf++;
+        float tc = ta, td = tb;
+        if (df != 0.0f) {
+            const float F0 = (float)j * cf - rr, F1 = (float)(j + 1) * cf - 1.0f + rr;
+            const float u1 = (F0 - gf) * inv_df, u2 = (F1 - gf) * inv_df;
+            tc = fmaxf(tc, fminf(u1, u2));
+            td = fminf(td, fmaxf(u1, u2));
+        }
+        const float xa = gx + tc * dx, xb = gx + td * dx;
+        const int x0 = max(0, (int)floorf(fmaxf((fminf(xa, xb) - rr) * icx, -1.0f)));
+        const int x1 = min(nx - 1, (int)floorf(fminf((fmaxf(xa, xb) + rr) * icx, (float)nx)));
+        if (tc > td || x0 > x1) return;
+        const int iy = e_is_y ? ie : j, iz = e_is_y ? j : ie;
+        const uint32_t row = off + (uint32_t)((iz * ny + iy) * nx);
+        out.k = cs[row + x0];
+        out.e = cs[row + x1 + 1];
+    }
+};
 
 // The cylinder predicate |(g_k - g_i) x d|^2 <= r^2 |d|^2, exact.
 // c = g_k x d - g_i x d is formed with 24-bit multiplies in wrapping 32-bit
-// arithmetic: coordinates are < 2^18 + 1 and |d_m| < 2^12, so every true
+// arithmetic: coordinates are in [0, 2^18] and |d_m| < 2^12, so every true
 // component of c is below 2^31 and the wrapped result equals it. |c|^2 is
 // compared in FP32 with a relative guard band of 2^-20 (the FP32 sum of
 // squares is within 5 * 2^-24 of exact); inside the band the test is redone
 // in int64.
 struct LineTest {
-    int dx, dy, dz;
     uint32_t ex, ey, ez;
     float tlo, thi;
     long long T;
 
-    __device__ __forceinline__ void init(int4 gi, int dx_, int dy_, int dz_, int r) {
-        dx = dx_;
-        dy = dy_;
-        dz = dz_;
+    __device__ __forceinline__ void init(int4 gi, int dx, int dy, int dz, int r) {
         ex = (uint32_t)__mul24(gi.y, dz) - (uint32_t)__mul24(gi.z, dy);
         ey = (uint32_t)__mul24(gi.z, dx) - (uint32_t)__mul24(gi.x, dz);
         ez = (uint32_t)__mul24(gi.x, dy) - (uint32_t)__mul24(gi.y, dx);
@@ -408,159 +460,358 @@ struct LineTest {
         tlo = tf * (1.0f - 0x1p-20f);
         thi = tf * (1.0f + 0x1p-20f);
     }
-
-    __device__ __forceinline__ bool hit(int4 h) const {
-        const int c0 = (int)((uint32_t)__mul24(h.y, dz) - (uint32_t)__mul24(h.z, dy) - ex);
-        const int c1 = (int)((uint32_t)__mul24(h.z, dx) - (uint32_t)__mul24(h.x, dz) - ey);
-        const int c2 = (int)((uint32_t)__mul24(h.x, dy) - (uint32_t)__mul24(h.y, dx) - ez);
-        const float f0 = (float)c0, f1 = (float)c1, f2 = (float)c2;
-        const float fc = fmaf(f0, f0, fmaf(f1, f1, f2 * f2));
-        if (fc <= tlo) return true;
-        if (fc > thi) return false;
-        const long long cc = (long long)c0 * c0 + (long long)c1 * c1 + (long long)c2 * c2;
-        return cc <= T;
-    }
 };
 
-struct CountOp {
-    LineTest L;
-    uint32_t n;
-    uint32_t tests;
-    __device__ __forceinline__ void operator()(uint32_t, int4 h) {
-        ++tests;
-        n += L.hit(h) ? 1u : 0u;
-    }
-};
-
-struct MemberOp {
-    LineTest L;
-    uint32_t *out;
-    uint32_t n, cap;
-    __device__ __forceinline__ void operator()(uint32_t k, int4 h) {
-        if (L.hit(h)) {
-            if (n < cap) out[n] = k;
-            ++n;
-        }
-    }
-};
+__device__ __forceinline__ bool cyl_hit(int4 h, int4 A, int4 B, const long long *T) {
+    // A = (dx, dy, dz, tlo), B = (ex, ey, ez, thi)
+    const int c0 = (int)((uint32_t)__mul24(h.y, A.z) - (uint32_t)__mul24(h.z, A.y) - (uint32_t)B.x);
+    const int c1 = (int)((uint32_t)__mul24(h.z, A.x) - (uint32_t)__mul24(h.x, A.z) - (uint32_t)B.y);
+    const int c2 = (int)((uint32_t)__mul24(h.x, A.y) - (uint32_t)__mul24(h.y, A.x) - (uint32_t)B.z);
+    const float f0 = (float)c0, f1 = (float)c1, f2 = (float)c2;
+    const float fc = fmaf(f0, f0, fmaf(f1, f1, f2 * f2));
+    if (fc <= __int_as_float(A.w)) return true;
+    if (fc > __int_as_float(B.w)) return false;
+    const long long cc = (long long)c0 * c0 + (long long)c1 * c1 + (long long)c2 * c2;
+    return cc <= *T;
+}
 
 // ----------------------------------------------------------------- seeds
-
-// One lane per anchor grain p: every grain q of the cells overlapping the
-// box [g_p - (R-1), g_p + (R-1)] with a higher input index and
-// 0 < |g_q - g_p|^2 < R^2 is a seed (p, q).
+//
+// One wave per anchor grain p; lanes take the (y, z) rows of the cell box
+// overlapping [g_p - (R-1), g_p + (R-1)]. Every grain q of those rows with a
+// higher input index and 0 < |g_q - g_p|^2 < R^2 makes a seed (p, q). A first
+// pass counts the seeds of every anchor, a scan turns the counts into
+// offsets, and a second pass writes them: no shared counter, and the seed
+// list comes out in anchor order.
+template <bool kWrite>
 __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
+    const int lane = lane_id();
+    const uint32_t gw = grid_tid() >> 6, nw = grid_threads() >> 6;
     const int R1 = P.R - 1;
     const int R2 = P.R * P.R;
-    for (uint32_t p = grid_tid(); p < c.n_total; p += grid_threads()) {
+    for (uint32_t p = gw; p < c.n_total; p += nw) {
         const uint32_t v = d.view_of[p];
         const ViewGrid *G = &d.grids[v];
-        if (G->err) continue;
-        const int nx = G->dims[0], ny = G->dims[1], nz = G->dims[2];
-        const int cx = G->cell[0], cy = G->cell[1], cz = G->cell[2];
-        const uint32_t off = G->cell_off;
-        const int4 g = d.sg[p];
-        const int x0 = g.x - R1 < 0 ? 0 : (g.x - R1) / cx;
-        const int y0 = g.y - R1 < 0 ? 0 : (g.y - R1) / cy;
-        const int z0 = g.z - R1 < 0 ? 0 : (g.z - R1) / cz;
-        const int x1 = min(nx - 1, (g.x + R1) / cx);
-        const int y1 = min(ny - 1, (g.y + R1) / cy);
-        const int z1 = min(nz - 1, (g.z + R1) / cz);
-        unsigned long long mine = 0;
-        for (int z = z0; z <= z1; ++z) {
-            for (int y = y0; y <= y1; ++y) {
-                const uint32_t row = off + (uint32_t)((z * ny + y) * nx);
-                const uint32_t k0 = d.cell_start[row + x0], k1 = d.cell_start[row + x1 + 1];
+        uint32_t base = kWrite ? d.seed_off[p] : 0u;
+        uint32_t mine = 0;
+        if (!G->err) {
+            const int nx = G->dims[0], ny = G->dims[1], nz = G->dims[2];
+            const int cx = G->cell[0], cy = G->cell[1], cz = G->cell[2];
+            const uint32_t off = G->cell_off;
+            const int4 g = d.sg[p];
+            const int x0 = g.x - R1 < 0 ? 0 : (g.x - R1) / cx;
+            const int y0 = g.y - R1 < 0 ? 0 : (g.y - R1) / cy;
+            const int z0 = g.z - R1 < 0 ? 0 : (g.z - R1) / cz;
+            const int x1 = min(nx - 1, (g.x + R1) / cx);
+            const int y1 = min(ny - 1, (g.y + R1) / cy);
+            const int z1 = min(nz - 1, (g.z + R1) / cz);
+            const int nyr = y1 - y0 + 1;
+            const int nrows = nyr * (z1 - z0 + 1);
+            for (int rb = 0; rb < nrows; rb += 64) {
+                const int rr = rb + lane;
+                uint32_t k0 = 0, k1 = 0;
+                if (rr < nrows) {
+                    const int y = y0 + rr % nyr, z = z0 + rr / nyr;
+                    const uint32_t row = off + (uint32_t)((z * ny + y) * nx);
+                    k0 = d.cell_start[row + x0];
+                    k1 = d.cell_start[row + x1 + 1];
+                }
                 for (uint32_t q = k0; q < k1; ++q) {
                     const int4 h = d.sg[q];
                     const int ex = h.x - g.x, ey = h.y - g.y, ez = h.z - g.z;
                     bool ok = h.w > g.w && abs(ex) <= R1 && abs(ey) <= R1 && abs(ez) <= R1;
                     const int D = ok ? ex * ex + ey * ey + ez * ez : 0;
                     ok = ok && D > 0 && D < R2;
-                    const unsigned long long slot = wave_append(ok, &d.cnt->n_seeds);
-                    if (ok) {
-                        ++mine;
-                        if (slot < c.seed_cap) d.seeds[slot] = make_uint2(p, q);
+                    if (kWrite) {
+                        const unsigned long long m = __ballot(ok);
+                        if (ok) {
+                            const unsigned long long slot =
+                                (unsigned long long)base + (unsigned long long)__popcll(m & lanes_below());
+                            if (slot < c.seed_cap) d.seeds[slot] = make_uint2(p, q);
+                        }
+                        base += (uint32_t)__popcll(m);
+                    } else {
+                        mine += ok ? 1u : 0u;
                     }
+                }
+                // lanes that left the row loop early missed later ballots:
+                // the running offset only grows, so the largest is current
+                if (kWrite) {
+                    for (int o = 32; o > 0; o >>= 1) base = max(base, __shfl_xor(base, o));
                 }
             }
         }
-        if (mine) atomicAdd(&d.view_seeds[v], mine);
-    }
-}
-
-// ----------------------------------------------------------------- count
-
-// One lane per seed: count the grains on its line; seeds reaching n_min are
-// appended to the candidate list with their priority key.
-__global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
-    const unsigned long long ns_all = d.cnt->n_seeds;
-    const unsigned long long ns = ns_all < c.seed_cap ? ns_all : c.seed_cap;
-    unsigned long long tests = 0, hits = 0;
-    for (unsigned long long s = grid_tid(); s < ns; s += grid_threads()) {
-        const uint2 pq = d.seeds[s];
-        const int4 gi = d.sg[pq.x], gj = d.sg[pq.y];
-        const uint32_t v = d.view_of[pq.x];
-        const int dx = gj.x - gi.x, dy = gj.y - gi.y, dz = gj.z - gi.z;
-        CountOp op;
-        op.L.init(gi, dx, dy, dz, P.r);
-        op.n = 0;
-        op.tests = 0;
-        walk_line(d.sg, d.cell_start, &d.grids[v], P.slab_x, gi.x, gi.y, gi.z, dx, dy, dz, P.r, op);
-        tests += op.tests;
-        hits += op.n;
-        const bool pred = op.n >= (uint32_t)P.n_min;
-        const uint32_t slot = wave_append32(pred, &d.cnt->n_cand);
-        if (pred) {
-            if (slot < c.cand_cap) {
-                Cand cd;
-                cd.p = pq.x;
-                cd.q = pq.y;
-                cd.n = op.n;
-                cd.v = v;
-                d.cand[slot] = cd;
-                d.key[slot] = cand_key(op.n, (uint32_t)gi.w, (uint32_t)gj.w);
-            }
-            atomicAdd(&d.view_cand[v], 1u);
+        if (!kWrite) {
+            mine = wave_sum(mine);
+            if (lane == 0) d.seed_cnt[p] = mine;
         }
     }
-    tests = wave_sum(tests);
-    hits = wave_sum(hits);
-    if (lane_id() == 0) {
-        atomicAdd(&d.cnt->tests, tests);
-        atomicAdd(&d.cnt->hits, hits);
+}
+
+__global__ void k_seed_total(DevPtrs d, Caps c) {
+    if (grid_tid() != 0) return;
+    // the scan total counts every seed; it wraps only above 2^32 - 1 per call
+    d.cnt->n_seeds = d.seed_off[c.n_total];
+}
+
+// ------------------------------------------------------- count / members
+//
+// One wave takes 64 seeds (count) or candidates (members), one per lane.
+// Each lane walks its own line four pencils per step, but instead of testing
+// the grains of a run itself it appends a run record (first grain, first
+// queue slot, owner lane) to a wave-private queue in LDS and marks the first
+// slot in a bit mask. When the queue fills, the wave tests 64 queued grains
+// per instruction: the run holding slot s is found by counting the marks up
+// to s, the line constants of its owner lane come from LDS, and hits are
+// counted with LDS atomics. Only the cheap walk is divergent across lanes;
+// the predicate work is dense.
+
+constexpr int kSlotCap = 2048;            // queued grain tests per wave
+constexpr int kRunCap = 768;              // queued runs per wave
+constexpr int kLaneCap = 16;              // grains one lane may queue per step
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaskWords = kSlotCap / 64;
+
+struct QueueLds {
+    int4 pa[64];  // dx, dy, dz, tlo
+    int4 pb[64];  // ex, ey, ez, thi
+    long long T[64];
+    uint32_t cnt[64];
+    uint32_t out_off[64];
+    uint32_t ncap[64];
+    unsigned long long mask[kMaskWords];  // bit s: a run starts at slot s
+    uint32_t before[kMaskWords];          // runs starting before word w
+    uint32_t run_k[kRunCap];              // first grain of the run
+    uint32_t run_tag[kRunCap];            // first slot | owner lane << 16
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t *tot) {
+    uint32_t x = v;
+    const int lane = lane_id();
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    *tot = __shfl(x, 63);
+    return x - v;
+}
+
+template <bool kMembers>
+__device__ __forceinline__ void flush_queue(QueueLds &Q, uint32_t qn, const int4 *__restrict__ sg,
+                                            uint32_t *__restrict__ members, int lane) {
+    wave_lds_sync();
+    const uint32_t nw = (qn + 63) >> 6;
+    {
+        const uint32_t c = (uint32_t)lane < nw ? (uint32_t)__popcll(Q.mask[lane]) : 0u;
+        uint32_t tot;
+        const uint32_t ex = wave_excl_scan(c, &tot);
+        if ((uint32_t)lane < nw) Q.before[lane] = ex;
+    }
+    wave_lds_sync();
+    const unsigned long long upto = (2ull << lane) - 1ull;  // bits 0..lane
+    for (uint32_t w = 0; w < nw; ++w) {
+        const uint32_t s = (w << 6) + (uint32_t)lane;
+        const unsigned long long word = Q.mask[w];
+        if (s < qn) {
+            const uint32_t r = Q.before[w] + (uint32_t)__popcll(word & upto) - 1u;
+            const uint32_t tag = Q.run_tag[r];
+            const uint32_t kk = Q.run_k[r] + (s - (tag & 0xffffu));
+            const uint32_t sl = tag >> 16;
+            const int4 h = sg[kk];
+            if (cyl_hit(h, Q.pa[sl], Q.pb[sl], &Q.T[sl])) {
+                const uint32_t pos = atomicAdd(&Q.cnt[sl], 1u);
+                if (kMembers && pos < Q.ncap[sl]) members[Q.out_off[sl] + pos] = kk;
+            }
+        }
+    }
+    wave_lds_sync();
+    if ((uint32_t)lane < nw) Q.mask[lane] = 0ull;
+    wave_lds_sync();
+}
+
+template <bool kMembers>
+__global__ void __launch_bounds__(kBlock) k_lines(DevPtrs d, Caps c, Params P) {
+    __shared__ QueueLds sQ[kWaves];
+    const int lane = lane_id();
+    QueueLds &Q = sQ[threadIdx.x >> 6];
+    unsigned long long n_items;
+    if (kMembers) {
+        const uint32_t nc = d.cnt->n_cand;
+        n_items = d.cnt->err ? 0ull : (nc < c.cand_cap ? nc : c.cand_cap);
+    } else {
+        const unsigned long long ns = d.cnt->n_seeds;
+        n_items = ns < c.seed_cap ? ns : c.seed_cap;
+    }
+    if (lane < kMaskWords) Q.mask[lane] = 0ull;
+    wave_lds_sync();
+    const unsigned long long gw = grid_tid() >> 6, nw = grid_threads() >> 6;
+    unsigned long long tests = 0, hits = 0;
+    for (unsigned long long base = gw * 64; base < n_items; base += nw * 64) {
+        const unsigned long long idx = base + (unsigned long long)lane;
+        const bool valid = idx < n_items;
+        uint32_t p = 0, q = 0, v = 0, ncap = 0, off = 0;
+        if (valid) {
+            if (kMembers) {
+                const Cand cd = d.cand[idx];
+                p = cd.p;
+                q = cd.q;
+                v = cd.v;
+                off = d.mem_off[idx];
+                ncap = ((unsigned long long)off + cd.n <= c.mem_cap) ? cd.n : 0u;
+            } else {
+                const uint2 pq = d.seeds[idx];
+                p = pq.x;
+                q = pq.y;
+                v = d.view_of[p];
+            }
+        }
+        const int4 gi = d.sg[p], gj = d.sg[q];
+        const int dx = gj.x - gi.x, dy = gj.y - gi.y, dz = gj.z - gi.z;
+        LineTest L;
+        L.init(gi, dx, dy, dz, P.r);
+        Q.pa[lane] = make_int4(dx, dy, dz, __float_as_int(L.tlo));
+        Q.pb[lane] = make_int4((int)L.ex, (int)L.ey, (int)L.ez, __float_as_int(L.thi));
+        Q.T[lane] = L.T;
+        Q.cnt[lane] = 0;
+        Q.out_off[lane] = off;
+        Q.ncap[lane] = ncap;
+        Pencil W;
+        W.init(&d.grids[v], gi, dx, dy, dz, P.r, valid && (!kMembers || ncap > 0));
+        Run s0 = {0, 0}, s1 = {0, 0}, s2 = {0, 0}, s3 = {0, 0};
+        uint32_t qn = 0, nr = 0;
+        for (;;) {
+            // refill the four run slots once all are used up: up to eight
+            // cell_start loads in flight before the first is needed
+            if (s0.k >= s0.e && s1.k >= s1.e && s2.k >= s2.e && s3.k >= s3.e && W.live) {
+                W.fetch(d.cell_start, s0);
+                W.fetch(d.cell_start, s1);
+                W.fetch(d.cell_start, s2);
+                W.fetch(d.cell_start, s3);
+            }
+            uint32_t budget = kLaneCap;
+            const uint32_t l0 = min(s0.e > s0.k ? s0.e - s0.k : 0u, budget);
+            budget -= l0;
+            const uint32_t l1 = min(s1.e > s1.k ? s1.e - s1.k : 0u, budget);
+            budget -= l1;
+            const uint32_t l2 = min(s2.e > s2.k ? s2.e - s2.k : 0u, budget);
+            budget -= l2;
+            const uint32_t l3 = min(s3.e > s3.k ? s3.e - s3.k : 0u, budget);
+            const uint32_t nrun = (l0 > 0) + (l1 > 0) + (l2 > 0) + (l3 > 0);
+            const uint32_t mine = l0 + l1 + l2 + l3;
+            uint32_t tot;
+            const uint32_t packed = wave_excl_scan(mine | (nrun << 16), &tot);
+            if (tot == 0) {
+                if (__ballot(W.live) == 0) break;
+                continue;
+            }
+            uint32_t pos = qn + (packed & 0xffffu);
+            uint32_t ri = nr + (packed >> 16);
+            const uint32_t tag = (uint32_t)lane << 16;
+            if (l0) {
+                Q.run_k[ri] = s0.k;
+                Q.run_tag[ri++] = pos | tag;
+                atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
+                pos += l0;
+                s0.k += l0;
+            }
+            if (l1) {
+                Q.run_k[ri] = s1.k;
+                Q.run_tag[ri++] = pos | tag;
+                atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
+                pos += l1;
+                s1.k += l1;
+            }
+            if (l2) {
+                Q.run_k[ri] = s2.k;
+                Q.run_tag[ri++] = pos | tag;
+                atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
+                pos += l2;
+                s2.k += l2;
+            }
+            if (l3) {
+                Q.run_k[ri] = s3.k;
+                Q.run_tag[ri] = pos | tag;
+                atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
+                s3.k += l3;
+            }
+            qn += tot & 0xffffu;
+            nr += tot >> 16;
+            tests += mine;
+            if (qn > (uint32_t)(kSlotCap - 64 * kLaneCap) || nr > (uint32_t)(kRunCap - 256)) {
+                flush_queue<kMembers>(Q, qn, d.sg, d.members, lane);
+                qn = 0;
+                nr = 0;
+            }
+        }
+        if (qn) flush_queue<kMembers>(Q, qn, d.sg, d.members, lane);
+        wave_lds_sync();
+        const uint32_t n = Q.cnt[lane];
+        if (kMembers) {
+            if (valid && ncap > 0 && n != ncap) {
+                // the same walk and predicate as the count: never expected;
+                // keep every entry a valid grain index and flag an internal error
+                for (uint32_t t = n; t < ncap; ++t) d.members[off + t] = p;
+                atomicOr(&d.cnt->err, 2u);
+            }
+        } else {
+            hits += valid ? n : 0u;
+            const bool pred = valid && n >= (uint32_t)P.n_min;
+            // a seed's count is kept only if it passes; a scan over these
+            // compacts the candidates in seed order
+            if (valid) d.seed_n[idx] = pred ? n : 0u;
+        }
+        wave_lds_sync();
+    }
+    if (!kMembers) {
+        tests = wave_sum(tests);
+        hits = wave_sum(hits);
+        if (lane == 0) {
+            atomicAdd(&d.cnt->tests, tests);
+            atomicAdd(&d.cnt->hits, hits);
+        }
     }
 }
 
-// --------------------------------------------------------------- members
+// Candidates in seed order: position from the flag scan of seed_n.
+__global__ void __launch_bounds__(kBlock) k_cand_scatter(DevPtrs d, Caps c) {
+    const uint32_t ns = min(d.cnt->n_seeds, (uint32_t)c.seed_cap);
+    for (uint32_t s = grid_tid(); s < ns; s += grid_threads()) {
+        const uint32_t n = d.seed_n[s];
+        if (!n) continue;
+        const uint32_t pos = d.cand_pos[s];
+        if (pos >= c.cand_cap) continue;
+        const uint2 pq = d.seeds[s];
+        Cand cd;
+        cd.p = pq.x;
+        cd.q = pq.y;
+        cd.n = n;
+        cd.v = d.view_of[pq.x];
+        d.cand[pos] = cd;
+        d.key[pos] = cand_key(n, (uint32_t)d.sg[pq.x].w, (uint32_t)d.sg[pq.y].w);
+    }
+}
+
+// Seeds and candidates of each view, from the offsets (views are contiguous
+// in anchor order, so in seed and in candidate order too).
+__global__ void k_view_counts(DevPtrs d, Caps c) {
+    const uint32_t v = grid_tid();
+    if (v >= c.n_views) return;
+    const uint32_t g0 = d.grids[v].grain_off, g1 = g0 + d.grids[v].n;
+    const uint32_t ns = min(d.cnt->n_seeds, (uint32_t)c.seed_cap);
+    const uint32_t s0 = d.seed_off[g0], s1 = d.seed_off[g1];
+    d.view_seeds[v] = s1 - s0;
+    d.view_cand[v] = d.cand_pos[min(s1, ns)] - d.cand_pos[min(s0, ns)];
+}
 
 __global__ void __launch_bounds__(kBlock) k_cand_n(DevPtrs d, Caps c) {
     const uint32_t nc = min(d.cnt->n_cand, c.cand_cap);
     for (uint32_t i = grid_tid(); i < nc; i += grid_threads()) d.cand_n[i] = d.cand[i].n;
-}
-
-__global__ void __launch_bounds__(kBlock) k_members(DevPtrs d, Caps c, Params P) {
-    const uint32_t nc = min(d.cnt->n_cand, c.cand_cap);
-    for (uint32_t i = grid_tid(); i < nc; i += grid_threads()) {
-        const Cand cd = d.cand[i];
-        const uint32_t off = d.mem_off[i];
-        if ((unsigned long long)off + cd.n > c.mem_cap) continue;
-        const int4 gi = d.sg[cd.p], gj = d.sg[cd.q];
-        const int dx = gj.x - gi.x, dy = gj.y - gi.y, dz = gj.z - gi.z;
-        MemberOp op;
-        op.L.init(gi, dx, dy, dz, P.r);
-        op.out = d.members + off;
-        op.n = 0;
-        op.cap = cd.n;
-        walk_line(d.sg, d.cell_start, &d.grids[cd.v], P.slab_x, gi.x, gi.y, gi.z, dx, dy, dz, P.r,
-                  op);
-        if (op.n != cd.n) {
-            // the same walk and predicate as the count: never expected; keep
-            // every entry a valid grain index and report an internal error
-            for (uint32_t t = op.n; t < cd.n; ++t) op.out[t] = cd.p;
-            atomicOr(&d.cnt->err, 2u);
-        }
-    }
 }
 
 // ----------------------------------------------------------------- merge
@@ -944,17 +1195,28 @@ void launch_bin(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s)
 }
 
 void launch_seeds(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
-    k_seeds<<<blocks_for(c.n_total, kPersistentBlocks), kBlock, 0, s>>>(d, c, P);
+    const uint32_t nb = blocks_for(64ull * c.n_total, 4 * kPersistentBlocks);
+    k_seeds<false><<<nb, kBlock, 0, s>>>(d, c, P);
+    scan_excl(d.seed_cnt, nullptr, c.n_total, d.scan_part, d.seed_off, nullptr, s);
+    k_seed_total<<<1, 64, 0, s>>>(d, c);
+    k_seeds<true><<<nb, kBlock, 0, s>>>(d, c, P);
 }
 
 void launch_count(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
-    k_count<<<blocks_for(c.seed_cap, kPersistentBlocks), kBlock, 0, s>>>(d, c, P);
+    k_lines<false><<<blocks_for(c.seed_cap, kPersistentBlocks), kBlock, 0, s>>>(d, c, P);
+}
+
+void launch_candidates(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {
+    scan_excl<true>(d.seed_n, &d.cnt->n_seeds, (uint32_t)c.seed_cap, d.scan_part, d.cand_pos,
+                    &d.cnt->n_cand, s);
+    k_cand_scatter<<<blocks_for(c.seed_cap, kPersistentBlocks), kBlock, 0, s>>>(d, c);
+    k_view_counts<<<(c.n_views + 63) / 64, 64, 0, s>>>(d, c);
 }
 
 void launch_members(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
     k_cand_n<<<blocks_for(c.cand_cap, 1024), kBlock, 0, s>>>(d, c);
     scan_excl(d.cand_n, &d.cnt->n_cand, c.cand_cap, d.scan_part, d.mem_off, &d.cnt->n_members, s);
-    k_members<<<blocks_for(c.cand_cap, kPersistentBlocks), kBlock, 0, s>>>(d, c, P);
+    k_lines<true><<<blocks_for(c.cand_cap, kPersistentBlocks), kBlock, 0, s>>>(d, c, P);
 }
 
 void launch_merge_init(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {
