@@ -25,7 +25,6 @@ constexpr uint32_t kKnownFlags = EMT_F_STATS | EMT_F_FP64_FIT_ALWAYS | EMT_F_DEV
 constexpr int kDefaultCellXY = 750;  // 7.5 um, the paper's 32-pixel hash cell
 constexpr int kDefaultCellZ = 500;
 constexpr int kMaxAttempts = 4;
-constexpr int kRoundChunk = 8;
 // seeds of one call are indexed by uint32 and scanned in uint32
 constexpr unsigned long long kSeedCapMax = (1ull << 31) - 1;
 
@@ -207,7 +206,7 @@ int ensure(emt_ctx *ctx, Caps &c) {
     if (c.cand_cap > ctx->cap_cand || !ctx->cand_buf.p) {
         const size_t n = c.cand_cap;
         const size_t b = bytes_of<Cand>(n) + bytes_of<unsigned long long>(n) +
-                         6 * bytes_of<uint32_t>(n + 1) + 4 * bytes_of<uint32_t>(n) +
+                         4 * bytes_of<uint32_t>(n + 1) + 6 * bytes_of<uint32_t>(n) +
                          bytes_of<uint8_t>(n) + bytes_of<emt_track>(n);
         if ((rc = arena(ctx, ctx->cand_buf, b))) return rc;
         char *p = (char *)ctx->cand_buf.p;
@@ -217,9 +216,9 @@ int ensure(emt_ctx *ctx, Caps &c) {
         d.mem_off = carve<uint32_t>(p, n + 1);
         d.tg_n = carve<uint32_t>(p, n + 1);
         d.tg_off = carve<uint32_t>(p, n + 1);
-        d.act[0] = carve<uint32_t>(p, n + 1);
-        d.act[1] = carve<uint32_t>(p, n + 1);
         d.mcount = carve<uint32_t>(p, n);
+        d.act = carve<uint32_t>(p, n);
+        d.act2 = carve<uint32_t>(p, n);
         d.acc = carve<uint32_t>(p, n);
         d.grouped = carve<uint32_t>(p, n);
         d.track_cand = carve<uint32_t>(p, n);
@@ -259,7 +258,8 @@ int ensure(emt_ctx *ctx, Caps &c) {
     if (c.n_views > ctx->cap_views || !ctx->view_buf.p) {
         const size_t n = std::max<uint32_t>(c.n_views, 64);
         const size_t b = bytes_of<ViewGrid>(n) + bytes_of<unsigned long long>(n) +
-                         4 * bytes_of<uint32_t>(n + 1) + bytes_of<Counters>(1);
+                         4 * bytes_of<uint32_t>(n + 1) + bytes_of<Counters>(1) +
+                         bytes_of<uint32_t>((size_t)max_merge_rounds());
         if ((rc = arena(ctx, ctx->view_buf, b))) return rc;
         char *p = (char *)ctx->view_buf.p;
         d.grids = carve<ViewGrid>(p, n);
@@ -269,6 +269,7 @@ int ensure(emt_ctx *ctx, Caps &c) {
         d.view_tr_off = carve<uint32_t>(p, n + 1);
         d.view_cursor = carve<uint32_t>(p, n + 1);
         d.cnt = carve<Counters>(p, 1);
+        d.undecided = carve<uint32_t>(p, (size_t)max_merge_rounds());
         ctx->cap_views = (uint32_t)n;
         // matching pinned host arrays
         size_t cap = 0;
@@ -345,18 +346,7 @@ int run_once(emt_ctx *ctx, const emt_view_in *views, uint32_t nv, const Caps &c,
     launch_members(run, c, ctx->P, s);
     record(ctx, 5);
     launch_merge_init(run, c, ctx->P, s);
-    int round = 0;
-    for (;;) {
-        for (int k = 0; k < kRoundChunk; ++k, ++round) launch_merge_round(run, c, ctx->P, round, s);
-        HIP_OK(hipMemcpyAsync(ctx->h_cnt, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
-        const Counters &h = *ctx->h_cnt;
-        if (h.n_seeds > c.seed_cap || h.n_cand > c.cand_cap || h.n_members > c.mem_cap) {
-            *overflow = true;
-            return EMT_EOVERFLOW;
-        }
-        if (h.n_act[round & 1] == 0) break;
-    }
+    launch_merge(run, c, ctx->P, s);
     record(ctx, 6);
     launch_fit(run, c, ctx->P, s);
     record(ctx, 7);
@@ -371,6 +361,17 @@ int run_once(emt_ctx *ctx, const emt_view_in *views, uint32_t nv, const Caps &c,
                           hipMemcpyDeviceToHost, s));
     HIP_OK(hipMemcpyAsync(ctx->h_grids, d.grids, sizeof(ViewGrid) * nv, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
+    {
+        const Counters &h = *ctx->h_cnt;
+        if (h.n_seeds > c.seed_cap || h.n_cand > c.cand_cap || h.n_members > c.mem_cap) {
+            *overflow = true;
+            return EMT_EOVERFLOW;
+        }
+        if (h.err & 4u) {
+            ctx->poisoned = true;
+            return EMT_EDEVICE;
+        }
+    }
     const uint32_t nt = ctx->h_cnt->n_acc, ng = ctx->h_cnt->n_track_grains;
     int rc;
     if ((rc = pinned(ctx, ctx->h_tracks, ctx->h_tracks_cap, nt))) return rc;
@@ -644,8 +645,8 @@ void emt_destroy(emt_ctx *ctx) {
     for (DevArena *a : arenas)
         if (a->p) (void)hipFree(a->p);
     void *hosts[] = {ctx->h_xyz, ctx->h_grids, ctx->h_view_seeds, ctx->h_view_cand,
-                     ctx->h_view_ntr, ctx->h_view_tr_off, ctx->h_cnt, ctx->h_tracks,
-                     ctx->h_grains};
+                     ctx->h_view_ntr, ctx->h_view_tr_off, ctx->h_cnt,
+                     ctx->h_tracks, ctx->h_grains};
     for (void *p : hosts)
         if (p) (void)hipHostFree(p);
     for (int i = 0; i <= EMT_N_STAGES; ++i)

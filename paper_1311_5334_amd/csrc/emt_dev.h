@@ -96,7 +96,9 @@ struct DevPtrs {
     uint32_t *mcount;     // cand_cap
     uint8_t *used;        // N
     unsigned long long *owner;  // N
-    uint32_t *act[2];     // cand_cap each
+    uint32_t *undecided;  // per merge round: nonzero if candidates stay undecided
+    uint32_t *act;        // cand_cap: undecided candidates handed to the tail
+    uint32_t *act2;       // cand_cap
     uint32_t *acc;        // cand_cap
     uint32_t *grouped;    // cand_cap
     uint32_t *track_cand; // cand_cap
@@ -133,10 +135,10 @@ void launch_count(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t 
 void launch_candidates(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
 void launch_members(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
 void launch_merge_init(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
-void launch_merge_round(const DevPtrs &d, const Caps &c, const Params &P, int round,
-                        hipStream_t s);
+void launch_merge(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
 void launch_fit(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
 
 size_t scan_scratch_words(uint32_t n_cap);
+int max_merge_rounds();
 
 }  // namespace emt

@@ -333,8 +333,10 @@ struct Pencil {
     float ta, tb;
     bool live;
 
+    // part/nparts: this lane walks the part-th of nparts equal slices of the
+    // e cells, so that several lanes can share one long line.
     __device__ __forceinline__ void init(const ViewGrid *__restrict__ Gp, int4 g, int idx, int idy,
-                                         int idz, int r, bool valid) {
+                                         int idz, int r, bool valid, int part, int nparts) {
         nx = Gp->dims[0];
         ny = Gp->dims[1];
         const int nz = Gp->dims[2];
@@ -375,8 +377,14 @@ struct Pencil {
         const float ea = ge + tlo * de, eb = ge + thi * de;
         const float elo = (de != 0.0f ? fminf(ea, eb) : ge) - rr;
         const float ehi = (de != 0.0f ? fmaxf(ea, eb) : ge) + rr;
-        const int ie0 = max(0, (int)floorf(fmaxf(elo / ce, -1.0f)));
+        int ie0 = max(0, (int)floorf(fmaxf(elo / ce, -1.0f)));
         ie1 = min(ne - 1, (int)floorf(fminf(ehi / ce, (float)ne)));
+        if (nparts > 1 && ie0 <= ie1) {
+            const int len = ie1 - ie0 + 1, per = (len + nparts - 1) / nparts;
+            const int a0 = ie0 + part * per;
+            ie1 = min(ie1, a0 + per - 1);
+            ie0 = a0;
+        }
         ie = ie0 - 1;
         jf = 1;
         jf1 = 0;
@@ -635,10 +643,12 @@ __device__ __forceinline__ void flush_queue(QueueLds &Q, uint32_t qn, const int4
     wave_lds_sync();
 }
 
-template <bool kMembers>
+template <bool kMembers, int kPer>
 __global__ void __launch_bounds__(kBlock) k_lines(DevPtrs d, Caps c, Params P) {
     __shared__ QueueLds sQ[kWaves];
     const int lane = lane_id();
+    const int slot = lane / kPer, sub = lane % kPer;
+    constexpr int kItems = 64 / kPer;
     QueueLds &Q = sQ[threadIdx.x >> 6];
     unsigned long long n_items;
     if (kMembers) {
@@ -652,8 +662,8 @@ __global__ void __launch_bounds__(kBlock) k_lines(DevPtrs d, Caps c, Params P) {
     wave_lds_sync();
     const unsigned long long gw = grid_tid() >> 6, nw = grid_threads() >> 6;
     unsigned long long tests = 0, hits = 0;
-    for (unsigned long long base = gw * 64; base < n_items; base += nw * 64) {
-        const unsigned long long idx = base + (unsigned long long)lane;
+    for (unsigned long long base = gw * kItems; base < n_items; base += nw * kItems) {
+        const unsigned long long idx = base + (unsigned long long)slot;
         const bool valid = idx < n_items;
         uint32_t p = 0, q = 0, v = 0, ncap = 0, off = 0;
         if (valid) {
@@ -675,14 +685,17 @@ __global__ void __launch_bounds__(kBlock) k_lines(DevPtrs d, Caps c, Params P) {
         const int dx = gj.x - gi.x, dy = gj.y - gi.y, dz = gj.z - gi.z;
         LineTest L;
         L.init(gi, dx, dy, dz, P.r);
-        Q.pa[lane] = make_int4(dx, dy, dz, __float_as_int(L.tlo));
-        Q.pb[lane] = make_int4((int)L.ex, (int)L.ey, (int)L.ez, __float_as_int(L.thi));
-        Q.T[lane] = L.T;
-        Q.cnt[lane] = 0;
-        Q.out_off[lane] = off;
-        Q.ncap[lane] = ncap;
+        if (sub == 0) {
+            Q.pa[slot] = make_int4(dx, dy, dz, __float_as_int(L.tlo));
+            Q.pb[slot] = make_int4((int)L.ex, (int)L.ey, (int)L.ez, __float_as_int(L.thi));
+            Q.T[slot] = L.T;
+            Q.cnt[slot] = 0;
+            Q.out_off[slot] = off;
+            Q.ncap[slot] = ncap;
+        }
+        wave_lds_sync();
         Pencil W;
-        W.init(&d.grids[v], gi, dx, dy, dz, P.r, valid && (!kMembers || ncap > 0));
+        W.init(&d.grids[v], gi, dx, dy, dz, P.r, valid && (!kMembers || ncap > 0), sub, kPer);
         Run s0 = {0, 0}, s1 = {0, 0}, s2 = {0, 0}, s3 = {0, 0};
         uint32_t qn = 0, nr = 0;
         for (;;) {
@@ -712,7 +725,7 @@ __global__ void __launch_bounds__(kBlock) k_lines(DevPtrs d, Caps c, Params P) {
             }
             uint32_t pos = qn + (packed & 0xffffu);
             uint32_t ri = nr + (packed >> 16);
-            const uint32_t tag = (uint32_t)lane << 16;
+            const uint32_t tag = (uint32_t)slot << 16;
             if (l0) {
                 Q.run_k[ri] = s0.k;
                 Q.run_tag[ri++] = pos | tag;
@@ -751,8 +764,10 @@ __global__ void __launch_bounds__(kBlock) k_lines(DevPtrs d, Caps c, Params P) {
         }
         if (qn) flush_queue<kMembers>(Q, qn, d.sg, d.members, lane);
         wave_lds_sync();
-        const uint32_t n = Q.cnt[lane];
-        if (kMembers) {
+        const uint32_t n = Q.cnt[slot];
+        if (sub != 0) {
+            // one lane per item reports
+        } else if (kMembers) {
             if (valid && ncap > 0 && n != ncap) {
                 // the same walk and predicate as the count: never expected;
                 // keep every entry a valid grain index and flag an internal error
@@ -818,13 +833,22 @@ __global__ void __launch_bounds__(kBlock) k_cand_n(DevPtrs d, Caps c) {
 //
 // Exclusive association, identical to taking candidates one by one in key
 // order: a candidate's outcome depends only on higher-priority candidates
-// that share one of its still unused grains. Each round, every undecided
-// candidate reserves its unused grains with an atomic min of its key. One
-// that holds every reservation has no undecided predecessor on its grains,
-// so its unused set is final: it is accepted if that set still has n_min
-// grains and takes them. A candidate left with fewer than n_min unused
-// grains is rejected at once (used grains never return). Accepted ones in
-// the same round own disjoint grains, so their updates do not interact.
+// that share one of its still unused grains. Each round:
+//   prune    a candidate left with fewer than n_min unused grains is
+//            rejected (used grains never return); the others clear the
+//            reservation of their unused grains;
+//   reserve  every undecided candidate takes an atomic min of its key on
+//            each of its unused grains;
+//   decide   one holding every reservation of its unused grains has no
+//            undecided predecessor on them, so its unused set is final: it
+//            is accepted with that set if it still has n_min grains.
+// Accepted candidates of one round own disjoint grains, so their updates do
+// not interact, and a concurrent update can only hide grains taken by a
+// higher-priority accepted candidate. One wave handles one candidate, lanes
+// its member entries; decided candidates cost one status read.
+
+constexpr int kMaxRounds = 256;
+constexpr int kWideRounds = 4;  // rounds run grid-wide before the tail kernel
 
 __global__ void __launch_bounds__(kBlock) k_merge_init(DevPtrs d, Caps c) {
     const Counters *cn = d.cnt;
@@ -833,7 +857,6 @@ __global__ void __launch_bounds__(kBlock) k_merge_init(DevPtrs d, Caps c) {
     const uint32_t nc = overflow ? 0u : cn->n_cand;
     const uint32_t nm = overflow ? 0u : cn->n_members;
     for (uint32_t i = grid_tid(); i < nc; i += grid_threads()) {
-        d.act[0][i] = i;
         d.status[i] = kUndecided;
         d.mcount[i] = 0;
     }
@@ -842,68 +865,180 @@ __global__ void __launch_bounds__(kBlock) k_merge_init(DevPtrs d, Caps c) {
         d.owner[g] = ~0ull;
     }
     for (uint32_t e = grid_tid(); e < nm; e += grid_threads()) d.taken[e] = 0;
+    for (uint32_t r = grid_tid(); r < kMaxRounds; r += grid_threads()) d.undecided[r] = 0;
     if (grid_tid() == 0) {
-        d.cnt->n_act[0] = nc;
-        d.cnt->n_act[1] = 0;
+        d.cnt->n_act[0] = nc;  // candidates taking part in the merge
+        d.cnt->n_act[1] = 0;   // candidates left for the tail kernel
         d.cnt->err |= overflow ? 1u : 0u;
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_round_reset(DevPtrs d, int cur) {
-    const uint32_t n = d.cnt->n_act[cur];
-    if (grid_tid() == 0) d.cnt->n_act[cur ^ 1] = 0;
-    for (uint32_t i = grid_tid(); i < n; i += grid_threads()) {
-        const uint32_t ci = d.act[cur][i];
-        const uint32_t e0 = d.mem_off[ci], e1 = e0 + d.cand[ci].n;
-        for (uint32_t e = e0; e < e1; ++e) d.owner[d.members[e]] = ~0ull;
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) k_round_reserve(DevPtrs d, int cur) {
-    const uint32_t n = d.cnt->n_act[cur];
-    for (uint32_t i = grid_tid(); i < n; i += grid_threads()) {
-        const uint32_t ci = d.act[cur][i];
+template <int kPhase>
+__global__ void __launch_bounds__(kBlock) k_round(DevPtrs d, Params P, int round, int append) {
+    const uint32_t n = d.cnt->n_act[0];
+    if (round > 0 && d.undecided[round - 1] == 0) return;
+    const int lane = lane_id();
+    const uint32_t gw = grid_tid() >> 6, nw = grid_threads() >> 6;
+    uint32_t still = 0;
+    for (uint32_t ci = gw; ci < n; ci += nw) {
+        if (d.status[ci] != kUndecided) continue;
         const unsigned long long key = d.key[ci];
-        const uint32_t e0 = d.mem_off[ci], e1 = e0 + d.cand[ci].n;
-        for (uint32_t e = e0; e < e1; ++e) {
-            const uint32_t k = d.members[e];
-            if (!d.used[k]) atomicMin(&d.owner[k], key);
-        }
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) k_round_decide(DevPtrs d, Params P, int cur) {
-    const uint32_t n = d.cnt->n_act[cur];
-    if (grid_tid() == 0 && n > 0) d.cnt->rounds += 1;
-    for (uint32_t i = grid_tid(); i < n; i += grid_threads()) {
-        const uint32_t ci = d.act[cur][i];
-        const unsigned long long key = d.key[ci];
-        const uint32_t e0 = d.mem_off[ci], e1 = e0 + d.cand[ci].n;
-        uint32_t unused = 0;
-        bool owns = true;
-        for (uint32_t e = e0; e < e1; ++e) {
-            const uint32_t k = d.members[e];
-            if (!d.used[k]) {
-                ++unused;
-                owns = owns && d.owner[k] == key;
-            }
-        }
-        if (unused < (uint32_t)P.n_min) {
-            d.status[ci] = kRejected;
-        } else if (owns) {
-            d.status[ci] = kAccepted;
-            d.mcount[ci] = unused;
-            for (uint32_t e = e0; e < e1; ++e) {
-                const uint32_t k = d.members[e];
+        const uint32_t e0 = d.mem_off[ci], ne = d.cand[ci].n;
+        if (kPhase == 0) {  // prune
+            uint32_t unused = 0;
+            for (uint32_t e = lane; e < ne; e += 64) {
+                const uint32_t k = d.members[e0 + e];
                 if (!d.used[k]) {
-                    d.used[k] = 1;
-                    d.taken[e] = 1;
+                    ++unused;
+                    d.owner[k] = ~0ull;
                 }
             }
-        } else {
-            const uint32_t slot = atomicAdd(&d.cnt->n_act[cur ^ 1], 1u);
-            d.act[cur ^ 1][slot] = ci;
+            unused = wave_sum(unused);
+            if (unused < (uint32_t)P.n_min && lane == 0) d.status[ci] = kRejected;
+        } else if (kPhase == 1) {  // reserve
+            for (uint32_t e = lane; e < ne; e += 64) {
+                const uint32_t k = d.members[e0 + e];
+                if (!d.used[k]) atomicMin(&d.owner[k], key);
+            }
+        } else {  // decide
+            uint32_t unused = 0;
+            bool owns = true;
+            for (uint32_t e = lane; e < ne; e += 64) {
+                const uint32_t k = d.members[e0 + e];
+                if (!d.used[k]) {
+                    ++unused;
+                    owns = owns && d.owner[k] == key;
+                }
+            }
+            unused = wave_sum(unused);
+            owns = __ballot(!owns) == 0;
+            if (unused < (uint32_t)P.n_min) {
+                if (lane == 0) d.status[ci] = kRejected;
+            } else if (owns) {
+                for (uint32_t e = lane; e < ne; e += 64) {
+                    const uint32_t k = d.members[e0 + e];
+                    if (!d.used[k]) {
+                        d.used[k] = 1;
+                        d.taken[e0 + e] = 1;
+                    }
+                }
+                if (lane == 0) {
+                    d.mcount[ci] = unused;
+                    d.status[ci] = kAccepted;
+                }
+            } else {
+                ++still;
+                if (append && lane == 0) {
+                    // the tail kernel continues from this list
+                    const uint32_t slot = atomicAdd(&d.cnt->n_act[1], 1u);
+                    d.act[slot] = ci;
+                }
+            }
         }
+    }
+    // only "any left" matters: every writer stores the same value
+    if (kPhase == 2 && lane == 0 && still) d.undecided[round] = 1u;
+}
+
+// The remaining rounds in one workgroup, looping until no candidate is
+// undecided (each round decides at least the highest-priority one, so it
+// ends within as many rounds as there are candidates). Waves take
+// candidates of the list; __syncthreads separates the phases.
+constexpr int kTailBlock = 1024;
+
+__global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, int last_round) {
+    __shared__ uint32_t s_n[2];
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    constexpr int kTailWaves = kTailBlock / 64;
+    if (threadIdx.x == 0) {
+        s_n[0] = d.undecided[last_round] ? d.cnt->n_act[1] : 0u;
+        s_n[1] = 0;
+    }
+    __syncthreads();
+    uint32_t *list[2] = {d.act, d.act2};
+    int cur = 0;
+    uint32_t rounds = 0;
+    const uint32_t limit = s_n[0] + 2;
+    while (s_n[cur] > 0 && rounds < limit) {
+        const uint32_t n = s_n[cur];
+        // prune
+        for (uint32_t i = wave; i < n; i += kTailWaves) {
+            const uint32_t ci = list[cur][i];
+            if (d.status[ci] != kUndecided) continue;
+            const uint32_t e0 = d.mem_off[ci], ne = d.cand[ci].n;
+            uint32_t unused = 0;
+            for (uint32_t e = lane; e < ne; e += 64) {
+                const uint32_t k = d.members[e0 + e];
+                if (!d.used[k]) {
+                    ++unused;
+                    d.owner[k] = ~0ull;
+                }
+            }
+            unused = wave_sum(unused);
+            if (unused < (uint32_t)P.n_min && lane == 0) d.status[ci] = kRejected;
+        }
+        __threadfence_block();
+        __syncthreads();
+        // reserve
+        for (uint32_t i = wave; i < n; i += kTailWaves) {
+            const uint32_t ci = list[cur][i];
+            if (d.status[ci] != kUndecided) continue;
+            const unsigned long long key = d.key[ci];
+            const uint32_t e0 = d.mem_off[ci], ne = d.cand[ci].n;
+            for (uint32_t e = lane; e < ne; e += 64) {
+                const uint32_t k = d.members[e0 + e];
+                if (!d.used[k]) atomicMin(&d.owner[k], key);
+            }
+        }
+        __threadfence_block();
+        __syncthreads();
+        // decide
+        for (uint32_t i = wave; i < n; i += kTailWaves) {
+            const uint32_t ci = list[cur][i];
+            if (d.status[ci] != kUndecided) continue;
+            const unsigned long long key = d.key[ci];
+            const uint32_t e0 = d.mem_off[ci], ne = d.cand[ci].n;
+            uint32_t unused = 0;
+            bool owns = true;
+            for (uint32_t e = lane; e < ne; e += 64) {
+                const uint32_t k = d.members[e0 + e];
+                if (!d.used[k]) {
+                    ++unused;
+                    owns = owns && d.owner[k] == key;
+                }
+            }
+            unused = wave_sum(unused);
+            owns = __ballot(!owns) == 0;
+            if (unused < (uint32_t)P.n_min) {
+                if (lane == 0) d.status[ci] = kRejected;
+            } else if (owns) {
+                for (uint32_t e = lane; e < ne; e += 64) {
+                    const uint32_t k = d.members[e0 + e];
+                    if (!d.used[k]) {
+                        d.used[k] = 1;
+                        d.taken[e0 + e] = 1;
+                    }
+                }
+                if (lane == 0) {
+                    d.mcount[ci] = unused;
+                    d.status[ci] = kAccepted;
+                }
+            } else if (lane == 0) {
+                const uint32_t slot = atomicAdd(&s_n[cur ^ 1], 1u);
+                list[cur ^ 1][slot] = ci;
+            }
+        }
+        __threadfence_block();
+        __syncthreads();
+        if (threadIdx.x == 0) s_n[cur] = 0;
+        cur ^= 1;
+        ++rounds;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d.cnt->rounds = (uint32_t)last_round + 1u + rounds;
+        if (s_n[cur] > 0) d.cnt->err |= 4u;
     }
 }
 
@@ -1203,7 +1338,7 @@ void launch_seeds(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t 
 }
 
 void launch_count(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
-    k_lines<false><<<blocks_for(c.seed_cap, kPersistentBlocks), kBlock, 0, s>>>(d, c, P);
+    k_lines<false, 1><<<blocks_for(c.seed_cap, kPersistentBlocks), kBlock, 0, s>>>(d, c, P);
 }
 
 void launch_candidates(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {
@@ -1216,7 +1351,7 @@ void launch_candidates(const DevPtrs &d, const Caps &c, const Params &, hipStrea
 void launch_members(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
     k_cand_n<<<blocks_for(c.cand_cap, 1024), kBlock, 0, s>>>(d, c);
     scan_excl(d.cand_n, &d.cnt->n_cand, c.cand_cap, d.scan_part, d.mem_off, &d.cnt->n_members, s);
-    k_lines<true><<<blocks_for(c.cand_cap, kPersistentBlocks), kBlock, 0, s>>>(d, c, P);
+    k_lines<true, 8><<<blocks_for(8ull * c.cand_cap, kPersistentBlocks), kBlock, 0, s>>>(d, c, P);
 }
 
 void launch_merge_init(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {
@@ -1226,14 +1361,17 @@ void launch_merge_init(const DevPtrs &d, const Caps &c, const Params &, hipStrea
     k_merge_init<<<blocks_for(n, kPersistentBlocks), kBlock, 0, s>>>(d, c);
 }
 
-void launch_merge_round(const DevPtrs &d, const Caps &c, const Params &P, int round,
-                        hipStream_t s) {
-    const int cur = round & 1;
-    const uint32_t nb = blocks_for(c.cand_cap, kPersistentBlocks);
-    k_round_reset<<<nb, kBlock, 0, s>>>(d, cur);
-    k_round_reserve<<<nb, kBlock, 0, s>>>(d, cur);
-    k_round_decide<<<nb, kBlock, 0, s>>>(d, P, cur);
+void launch_merge(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
+    const uint32_t nb = blocks_for(64ull * c.cand_cap, 4 * kPersistentBlocks);
+    for (int round = 0; round < kWideRounds; ++round) {
+        k_round<0><<<nb, kBlock, 0, s>>>(d, P, round, 0);
+        k_round<1><<<nb, kBlock, 0, s>>>(d, P, round, 0);
+        k_round<2><<<nb, kBlock, 0, s>>>(d, P, round, round == kWideRounds - 1);
+    }
+    k_merge_tail<<<1, kTailBlock, 0, s>>>(d, P, kWideRounds - 1);
 }
+
+int max_merge_rounds() { return kMaxRounds; }
 
 void launch_fit(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
     const uint32_t nb = blocks_for(c.cand_cap, kPersistentBlocks);
