@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -443,12 +444,22 @@ int emt_create(const emt_config *cfg, emt_ctx **out) {
     ctx->P.R = cfg->seed_dist;
     ctx->P.r = cfg->tol_radius;
     ctx->P.n_min = cfg->min_grains;
-    ctx->P.slab_x = 1;
+    ctx->P.count_lanes = 1;
     ctx->P.cell_req[0] = cfg->cell_xy ? cfg->cell_xy : kDefaultCellXY;
     ctx->P.cell_req[1] = cfg->cell_xy ? cfg->cell_xy : kDefaultCellXY;
     ctx->P.cell_req[2] = cfg->cell_z ? cfg->cell_z : kDefaultCellZ;
     ctx->P.flags = cfg->flags;
-    if (const char *e = std::getenv("EMT_SLAB_X")) ctx->P.slab_x = std::max(1, std::atoi(e));
+    // Tuning hooks: cell edges "x,y,z" in units, and lanes per seed line.
+    if (const char *e = std::getenv("EMT_CELL")) {
+        int v[3];
+        if (std::sscanf(e, "%d,%d,%d", &v[0], &v[1], &v[2]) == 3 && v[0] > 0 && v[1] > 0 &&
+            v[2] > 0 && v[0] <= kSpanMax && v[1] <= kSpanMax && v[2] <= kSpanMax)
+            for (int m = 0; m < 3; ++m) ctx->P.cell_req[m] = v[m];
+    }
+    if (const char *e = std::getenv("EMT_COUNT_LANES")) {
+        const int k = std::atoi(e);
+        ctx->P.count_lanes = (k >= 4) ? 4 : (k >= 2 ? 2 : 1);
+    }
     // Test hook: start from tiny capacities so the first call overflows and
     // the retry path runs.
     if (const char *e = std::getenv("EMT_INITIAL_CAPS")) {

@@ -32,7 +32,7 @@ struct ViewGrid {
 };
 
 struct Params {
-    int32_t R, r, n_min, slab_x;
+    int32_t R, r, n_min, count_lanes;
     int32_t cell_req[3];
     uint32_t flags;
 };

@@ -324,61 +324,99 @@ struct Run {
 };
 
 struct Pencil {
-    float gx, dx, ge, de, gf, df, inv_de, inv_df;
-    float rr, tlo, thi, icx, ce, cf;
+    // per line: x origin and direction, e/f axis data, parameter bounds
+    float gx, dx, gf, df, rr, tlo, thi, icx, icf;
+    float ue0, ues, uew;  // e cell j spans parameters [ue0 + j ues, + uew] (any order)
+    float uf0, ufs, ufw;  // f cell j likewise
     int nx, ny, nf;
     uint32_t off;
     bool e_is_y;
+    // walk state: e cell ie of [.., ie1], f cells [jf, jf1] of it
     int ie, ie1, jf, jf1;
     float ta, tb;
     bool live;
 
     // part/nparts: this lane walks the part-th of nparts equal slices of the
-    // e cells, so that several lanes can share one long line.
+    // e cells, so that several lanes can share one long line. No divisions:
+    // reciprocals (within 1 ulp) are covered by the kMargin widening.
     __device__ __forceinline__ void init(const ViewGrid *__restrict__ Gp, int4 g, int idx, int idy,
                                          int idz, int r, bool valid, int part, int nparts) {
         nx = Gp->dims[0];
         ny = Gp->dims[1];
         const int nz = Gp->dims[2];
-        const float cx = (float)Gp->cell[0], cy = (float)Gp->cell[1], cz = (float)Gp->cell[2];
+        const int cxi = Gp->cell[0], cyi = Gp->cell[1], czi = Gp->cell[2];
         off = Gp->cell_off;
         rr = (float)r + kMargin;
-        icx = 1.0f / cx;
+        icx = __builtin_amdgcn_rcpf((float)cxi);
         gx = (float)g.x;
         dx = (float)idx;
         const float gy = (float)g.y, gz = (float)g.z, dy = (float)idy, dz = (float)idz;
+        const float ix = idx ? __builtin_amdgcn_rcpf(dx) : 0.0f;
+        const float iy = idy ? __builtin_amdgcn_rcpf(dy) : 0.0f;
+        const float iz = idz ? __builtin_amdgcn_rcpf(dz) : 0.0f;
         // parameter range in which the line is within rr of the grid box
-        tlo = -3.0e38f;
-        thi = 3.0e38f;
-        const float gm[3] = {gx, gy, gz}, dm[3] = {dx, dy, dz};
-        const float hm[3] = {(float)(nx * Gp->cell[0] - 1), (float)(ny * Gp->cell[1] - 1),
-                             (float)(nz * Gp->cell[2] - 1)};
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            if (dm[m] != 0.0f) {
-                const float t1 = (-rr - gm[m]) / dm[m];
-                const float t2 = (hm[m] + rr - gm[m]) / dm[m];
-                tlo = fmaxf(tlo, fminf(t1, t2));
-                thi = fminf(thi, fmaxf(t1, t2));
-            }
+        constexpr float kBig = 3.0e38f;
+        float t1, t2;
+        tlo = -kBig;
+        thi = kBig;
+        if (idx) {
+            t1 = (-rr - gx) * ix;
+            t2 = ((float)(nx * cxi - 1) + rr - gx) * ix;
+            tlo = fmaxf(tlo, fminf(t1, t2));
+            thi = fminf(thi, fmaxf(t1, t2));
         }
-        e_is_y = fabsf(dy) >= fabsf(dz);
-        ge = e_is_y ? gy : gz;
-        de = e_is_y ? dy : dz;
+        if (idy) {
+            t1 = (-rr - gy) * iy;
+            t2 = ((float)(ny * cyi - 1) + rr - gy) * iy;
+            tlo = fmaxf(tlo, fminf(t1, t2));
+            thi = fminf(thi, fmaxf(t1, t2));
+        }
+        if (idz) {
+            t1 = (-rr - gz) * iz;
+            t2 = ((float)(nz * czi - 1) + rr - gz) * iz;
+            tlo = fmaxf(tlo, fminf(t1, t2));
+            thi = fminf(thi, fmaxf(t1, t2));
+        }
+        e_is_y = abs(idy) >= abs(idz);
+        const float ge = e_is_y ? gy : gz;
+        const float de = e_is_y ? dy : dz;
+        const float ie_ = e_is_y ? iy : iz;
+        const float ce = (float)(e_is_y ? cyi : czi);
+        const int ne = e_is_y ? ny : nz;
         gf = e_is_y ? gz : gy;
         df = e_is_y ? dz : dy;
-        ce = e_is_y ? cy : cz;
-        cf = e_is_y ? cz : cy;
-        const int ne = e_is_y ? ny : nz;
+        const float if_ = e_is_y ? iz : iy;
+        const float cf = (float)(e_is_y ? czi : cyi);
         nf = e_is_y ? nz : ny;
-        inv_de = de != 0.0f ? 1.0f / de : 0.0f;
-        inv_df = df != 0.0f ? 1.0f / df : 0.0f;
+        const float ice = __builtin_amdgcn_rcpf(ce);
+        icf = __builtin_amdgcn_rcpf(cf);
+        // cell j of an axis with direction d != 0 is met for parameters
+        // [(j c - rr - g)/d, ((j+1) c - 1 + rr - g)/d]; with d == 0 every
+        // visited cell is met for all parameters
+        if (de != 0.0f) {
+            ue0 = (-rr - ge) * ie_;
+            ues = ce * ie_;
+            uew = (ce - 1.0f + 2.0f * rr) * ie_;
+        } else {
+            ue0 = -kBig;
+            ues = 0.0f;
+            uew = 2.0f * kBig;
+        }
+        if (df != 0.0f) {
+            uf0 = (-rr - gf) * if_;
+            ufs = cf * if_;
+            ufw = (cf - 1.0f + 2.0f * rr) * if_;
+        } else {
+            uf0 = -kBig;
+            ufs = 0.0f;
+            ufw = 2.0f * kBig;
+        }
         // e cells the widened projection touches
         const float ea = ge + tlo * de, eb = ge + thi * de;
         const float elo = (de != 0.0f ? fminf(ea, eb) : ge) - rr;
         const float ehi = (de != 0.0f ? fmaxf(ea, eb) : ge) + rr;
-        int ie0 = max(0, (int)floorf(fmaxf(elo / ce, -1.0f)));
-        ie1 = min(ne - 1, (int)floorf(fminf(ehi / ce, (float)ne)));
+        int ie0 = max(0, (int)floorf(fmaxf(elo * ice, -1.0f)));
+        ie1 = min(ne - 1, (int)floorf(fminf(ehi * ice, (float)ne)));
         if (nparts > 1 && ie0 <= ie1) {
             const int len = ie1 - ie0 + 1, per = (len + nparts - 1) / nparts;
             const int a0 = ie0 + part * per;
@@ -392,57 +430,39 @@ struct Pencil {
         live = valid && ie0 <= ie1 && tlo <= thi;
     }
 
-    // Parameter interval and f cells of e cell ie.
-    __device__ __forceinline__ void setup_e() {
-        const float E0 = (float)ie * ce - rr, E1 = (float)(ie + 1) * ce - 1.0f + rr;
-        if (de != 0.0f) {
-            const float t1 = (E0 - ge) * inv_de, t2 = (E1 - ge) * inv_de;
-            ta = fmaxf(tlo, fminf(t1, t2));
-            tb = fminf(thi, fmaxf(t1, t2));
-        } else {
-            ta = tlo;
-            tb = (ge >= E0 && ge <= E1) ? thi : tlo - 1.0f;
-        }
-        if (ta > tb) {
-            jf = 1;
-            jf1 = 0;
-            return;
-        }
-        const float fa = gf + ta * df, fb = gf + tb * df;
-        jf = max(0, (int)floorf(fmaxf((fminf(fa, fb) - rr) / cf, -1.0f)));
-        jf1 = min(nf - 1, (int)floorf(fminf((fmaxf(fa, fb) + rr) / cf, (float)nf)));
-    }
-
-    // One move of the walk: the next f cell of the current e cell (or the
-    // set-up of the next e cell). Fills out with that pencil's run, or an
-    // empty run; the two cell_start loads are issued but not waited on.
+    // One move of the walk, straight-line: step to the next e cell when the
+    // current one is used up, then take the next f cell of it. Fills out
+    // with that pencil's run or an empty run; the two cell_start loads are
+    // issued but not waited on.
     __device__ __forceinline__ void fetch(const uint32_t *__restrict__ cs, Run &out) {
-        out.k = out.e = 0;
-        if (!live) return;
-        if (jf > jf1) {
-            if (++ie > ie1) {
-                live = false;
-                return;
-            }
-            setup_e();
-            if (jf > jf1) return;
+        // set-up of e cell ie + 1, taken if the current one is used up
+        const bool step_e = jf > jf1;
+        const int ien = ie + 1;
+        const float e1 = fmaf((float)ien, ues, ue0), e2 = e1 + uew;
+        const float tan_ = fmaxf(tlo, fminf(e1, e2)), tbn = fminf(thi, fmaxf(e1, e2));
+        const float fa = fmaf(tan_, df, gf), fb = fmaf(tbn, df, gf);
+        const int jf0n = max(0, (int)floorf(fmaxf((fminf(fa, fb) - rr) * icf, -1.0f)));
+        const int jf1n = min(nf - 1, (int)floorf(fminf((fmaxf(fa, fb) + rr) * icf, (float)nf)));
+        if (step_e) {
+            ie = ien;
+            ta = tan_;
+            tb = tbn;
+            jf = tan_ <= tbn ? jf0n : 1;
+            jf1 = tan_ <= tbn ? jf1n : 0;
         }
-        const int j = jf++;
-        float tc = ta, td = tb;
-        if (df != 0.0f) {
-            const float F0 = (float)j * cf - rr, F1 = (float)(j + 1) * cf - 1.0f + rr;
-            const float u1 = (F0 - gf) * inv_df, u2 = (F1 - gf) * inv_df;
-            tc = fmaxf(tc, fminf(u1, u2));
-            td = fminf(td, fmaxf(u1, u2));
-        }
-        const float xa = gx + tc * dx, xb = gx + td * dx;
+        live = live && ie <= ie1;
+        const int j = jf;
+        const float f1 = fmaf((float)j, ufs, uf0), f2 = f1 + ufw;
+        const float tc = fmaxf(ta, fminf(f1, f2)), td = fminf(tb, fmaxf(f1, f2));
+        const float xa = fmaf(tc, dx, gx), xb = fmaf(td, dx, gx);
         const int x0 = max(0, (int)floorf(fmaxf((fminf(xa, xb) - rr) * icx, -1.0f)));
         const int x1 = min(nx - 1, (int)floorf(fminf((fmaxf(xa, xb) + rr) * icx, (float)nx)));
-        if (tc > td || x0 > x1) return;
+        const bool ok = live && j <= jf1 && tc <= td && x0 <= x1;
+        jf = j + 1;
         const int iy = e_is_y ? ie : j, iz = e_is_y ? j : ie;
         const uint32_t row = off + (uint32_t)((iz * ny + iy) * nx);
-        out.k = cs[row + x0];
-        out.e = cs[row + x1 + 1];
+        out.k = ok ? cs[row + x0] : 0u;
+        out.e = ok ? cs[row + x1 + 1] : 0u;
     }
 };
 
@@ -608,6 +628,19 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t *tot) {
     }
     *tot = __shfl(x, 63);
     return x - v;
+}
+
+// Inclusive prefix sum over the 64 lanes with DPP row shifts and row
+// broadcasts (no LDS traffic).
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t x) {
+    uint32_t v = x;
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
 }
 
 template <bool kMembers>
@@ -790,6 +823,207 @@ __global__ void __launch_bounds__(kBlock) k_lines(DevPtrs d, Caps c, Params P) {
             atomicAdd(&d.cnt->tests, tests);
             atomicAdd(&d.cnt->hits, hits);
         }
+    }
+}
+
+// Counting with lane refill. A wave owns a chunk of seeds; each lane holds
+// two seed slots in LDS. When a lane's walk ends it closes that slot and at
+// once takes the next seed of the chunk into its other slot, so the wave's
+// time is the sum of its lines' work rather than a multiple of the longest
+// one. Hit counts of a closed slot are final after the next queue flush,
+// which writes them out and frees the slot.
+constexpr int kCountSlots = 128;
+constexpr int kCountSlotCap = 1024;
+constexpr int kCountRunCap = 512;
+constexpr int kCountLaneCap = 8;
+constexpr int kCountMaskWords = kCountSlotCap / 64;
+constexpr int kChunkSeeds = 64;
+
+struct CountLds {
+    int4 pa[kCountSlots];
+    int4 pb[kCountSlots];
+    long long T[kCountSlots];
+    uint32_t cnt[kCountSlots];
+    unsigned long long mask[kCountMaskWords];
+    uint32_t before[kCountMaskWords];
+    uint32_t run_k[kCountRunCap];
+    uint32_t run_tag[kCountRunCap];  // first queue slot | seed slot << 16
+};
+
+__device__ __forceinline__ void count_flush(CountLds &Q, uint32_t qn, const int4 *__restrict__ sg,
+                                            int lane) {
+    wave_lds_sync();
+    const uint32_t nw = (qn + 63) >> 6;
+    {
+        const uint32_t c = (uint32_t)lane < nw ? (uint32_t)__popcll(Q.mask[lane]) : 0u;
+        const uint32_t incl = wave_incl_scan_dpp(c);
+        if ((uint32_t)lane < nw) Q.before[lane] = incl - c;
+    }
+    wave_lds_sync();
+    const unsigned long long upto = (2ull << lane) - 1ull;
+    for (uint32_t w = 0; w < nw; ++w) {
+        const uint32_t s = (w << 6) + (uint32_t)lane;
+        const unsigned long long word = Q.mask[w];
+        if (s < qn) {
+            const uint32_t r = Q.before[w] + (uint32_t)__popcll(word & upto) - 1u;
+            const uint32_t tag = Q.run_tag[r];
+            const uint32_t kk = Q.run_k[r] + (s - (tag & 0xffffu));
+            const uint32_t sl = tag >> 16;
+            const int4 h = sg[kk];
+            if (cyl_hit(h, Q.pa[sl], Q.pb[sl], &Q.T[sl])) atomicAdd(&Q.cnt[sl], 1u);
+        }
+    }
+    wave_lds_sync();
+    if ((uint32_t)lane < nw) Q.mask[lane] = 0ull;
+    wave_lds_sync();
+}
+
+__global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
+    __shared__ CountLds sQ[kWaves];
+    const int lane = lane_id();
+    CountLds &Q = sQ[threadIdx.x >> 6];
+    const unsigned long long ns = d.cnt->n_seeds;
+    const uint32_t n_items = (uint32_t)(ns < c.seed_cap ? ns : c.seed_cap);
+    if (lane < kCountMaskWords) Q.mask[lane] = 0ull;
+    wave_lds_sync();
+    const uint32_t gw = grid_tid() >> 6, nwv = grid_threads() >> 6;
+    unsigned long long tests = 0, hits = 0;
+    // this wave's chunks: gw, gw + nwv, gw + 2 nwv, ... of kChunkSeeds seeds;
+    // lanes move on to the next chunk as soon as the current one is taken
+    uint32_t chunk = gw * kChunkSeeds;
+    uint32_t next = min(chunk, n_items), end = min(n_items, chunk + kChunkSeeds);
+    bool have = false;
+    bool pend0 = false, pend1 = false;  // slot closed, count not yet written
+    uint32_t idx0 = 0, idx1 = 0;        // seed index held by each slot
+    int cur = lane;
+    Pencil W;
+    W.live = false;
+    Run s0 = {0, 0}, s1 = {0, 0}, s2 = {0, 0}, s3 = {0, 0};
+    uint32_t qn = 0, nr = 0;
+    for (;;) {
+        {
+            if (next >= end && chunk + nwv * kChunkSeeds < n_items) {
+                chunk += nwv * kChunkSeeds;
+                next = chunk;
+                end = min(n_items, chunk + kChunkSeeds);
+            }
+            // take the next seeds into free slots
+            const bool want = !have && !(pend0 && pend1);
+            const unsigned long long wm = __ballot(want);
+            const uint32_t rank = (uint32_t)__popcll(wm & lanes_below());
+            const bool take = want && next + rank < end;
+            if (take) {
+                const uint32_t idx = next + rank;
+                cur = pend0 ? lane + 64 : lane;
+                if (cur == lane) idx0 = idx; else idx1 = idx;
+                const uint2 pq = d.seeds[idx];
+                const uint32_t v = d.view_of[pq.x];
+                const int4 gi = d.sg[pq.x], gj = d.sg[pq.y];
+                const int dx = gj.x - gi.x, dy = gj.y - gi.y, dz = gj.z - gi.z;
+                LineTest L;
+                L.init(gi, dx, dy, dz, P.r);
+                Q.pa[cur] = make_int4(dx, dy, dz, __float_as_int(L.tlo));
+                Q.pb[cur] = make_int4((int)L.ex, (int)L.ey, (int)L.ez, __float_as_int(L.thi));
+                Q.T[cur] = L.T;
+                Q.cnt[cur] = 0;
+                W.init(&d.grids[v], gi, dx, dy, dz, P.r, true, 0, 1);
+                have = true;
+            }
+            next = min(end, next + (uint32_t)__popcll(wm));
+            // fetch four runs once the previous four are queued
+            if (have && W.live && s0.k >= s0.e && s1.k >= s1.e && s2.k >= s2.e && s3.k >= s3.e) {
+                W.fetch(d.cell_start, s0);
+                W.fetch(d.cell_start, s1);
+                W.fetch(d.cell_start, s2);
+                W.fetch(d.cell_start, s3);
+            }
+            uint32_t budget = kCountLaneCap;
+            const uint32_t l0 = min(s0.e > s0.k ? s0.e - s0.k : 0u, budget);
+            budget -= l0;
+            const uint32_t l1 = min(s1.e > s1.k ? s1.e - s1.k : 0u, budget);
+            budget -= l1;
+            const uint32_t l2 = min(s2.e > s2.k ? s2.e - s2.k : 0u, budget);
+            budget -= l2;
+            const uint32_t l3 = min(s3.e > s3.k ? s3.e - s3.k : 0u, budget);
+            const uint32_t nrun = (l0 > 0) + (l1 > 0) + (l2 > 0) + (l3 > 0);
+            const uint32_t mine = l0 + l1 + l2 + l3;
+            const uint32_t pk = mine | (nrun << 16);
+            const uint32_t incl = wave_incl_scan_dpp(pk);
+            const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+            const uint32_t ex = incl - pk;
+            if (mine) {
+                uint32_t pos = qn + (ex & 0xffffu);
+                uint32_t ri = nr + (ex >> 16);
+                const uint32_t tag = (uint32_t)cur << 16;
+                if (l0) {
+                    Q.run_k[ri] = s0.k;
+                    Q.run_tag[ri++] = pos | tag;
+                    atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
+                    pos += l0;
+                    s0.k += l0;
+                }
+                if (l1) {
+                    Q.run_k[ri] = s1.k;
+                    Q.run_tag[ri++] = pos | tag;
+                    atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
+                    pos += l1;
+                    s1.k += l1;
+                }
+                if (l2) {
+                    Q.run_k[ri] = s2.k;
+                    Q.run_tag[ri++] = pos | tag;
+                    atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
+                    pos += l2;
+                    s2.k += l2;
+                }
+                if (l3) {
+                    Q.run_k[ri] = s3.k;
+                    Q.run_tag[ri] = pos | tag;
+                    atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
+                    s3.k += l3;
+                }
+            }
+            qn += tot & 0xffffu;
+            nr += tot >> 16;
+            tests += mine;
+            // a seed whose walk ended and whose runs are all queued is closed
+            if (have && !W.live && s0.k >= s0.e && s1.k >= s1.e && s2.k >= s2.e &&
+                s3.k >= s3.e) {
+                have = false;
+                if (cur == lane) pend0 = true; else pend1 = true;
+            }
+            const bool blocked = !have && pend0 && pend1;
+            const uint32_t n_blocked = (uint32_t)__popcll(__ballot(blocked));
+            const bool more = chunk + nwv * kChunkSeeds < n_items;
+            const bool all_done = __ballot(have) == 0 && next >= end && !more;
+            if (all_done || qn > (uint32_t)(kCountSlotCap - 64 * kCountLaneCap) ||
+                nr > (uint32_t)(kCountRunCap - 256) || n_blocked > 16) {
+                if (qn) count_flush(Q, qn, d.sg, lane);
+                qn = 0;
+                nr = 0;
+                // every closed slot is final now
+                if (pend0) {
+                    const uint32_t n = Q.cnt[lane];
+                    hits += n;
+                    d.seed_n[idx0] = n >= (uint32_t)P.n_min ? n : 0u;
+                    pend0 = false;
+                }
+                if (pend1) {
+                    const uint32_t n = Q.cnt[lane + 64];
+                    hits += n;
+                    d.seed_n[idx1] = n >= (uint32_t)P.n_min ? n : 0u;
+                    pend1 = false;
+                }
+                wave_lds_sync();
+                if (all_done) break;
+            }
+        }
+    }
+    tests = wave_sum(tests);
+    hits = wave_sum(hits);
+    if (lane == 0) {
+        atomicAdd(&d.cnt->tests, tests);
+        atomicAdd(&d.cnt->hits, hits);
     }
 }
 
@@ -1338,7 +1572,13 @@ void launch_seeds(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t 
 }
 
 void launch_count(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
-    k_lines<false, 1><<<blocks_for(c.seed_cap, kPersistentBlocks), kBlock, 0, s>>>(d, c, P);
+    if (P.count_lanes >= 2) {
+        // batch form: 64 seeds per wave, kept for comparison runs
+        const uint32_t nb = blocks_for(c.seed_cap, kPersistentBlocks);
+        k_lines<false, 1><<<nb, kBlock, 0, s>>>(d, c, P);
+        return;
+    }
+    k_count<<<kPersistentBlocks, kBlock, 0, s>>>(d, c, P);
 }
 
 void launch_candidates(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {
