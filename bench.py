@@ -69,6 +69,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--view-index", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 256 MiB device copy, the reference "
+                         "for scaling FETCH_SIZE/WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); views are "
@@ -82,6 +85,13 @@ def main() -> int:
     view = synth.make_c2(args.view_index)
     dev = torch.from_numpy(view.xyz).to("cuda:0").contiguous()
     torch.cuda.synchronize()
+    if args.calibrate_copy:
+        src = torch.empty(64 << 20, dtype=torch.int32, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     tr = emt.Tracker(device=0, flags=emt.EMT_F_DEVICE_PTRS | emt.EMT_F_STATS)
     for _ in range(args.warmup):
         tr([dev])

@@ -63,10 +63,10 @@ extern "C" {
  *   tol_radius  r in units (default 50 = 0.5 um); 0 <= r < R. Inclusive.
  *   min_grains  n_min (default 8); 2 <= n_min < 2^20. Applied to the count
  *               and again after exclusive association.
- *   cell_xy     edge of a hash cell in x and y, units (0 = library choice).
- *   cell_z      edge of a hash cell in z, units (0 = library choice).
- *               Cells only steer the work (paper Sec. 3 footnote), never the
- *               result.
+ *   cell        edge of a hash cell along x, y, z in units (0 = library
+ *               choice: 250, 750, 500). Cells only steer the work (paper
+ *               Sec. 3 footnote), never the result; the library widens them
+ *               if a view would need more than 4N + 4096 cells.
  *   device      HIP device ordinal.
  *   flags       EMT_F_* bits.
  *   hbm_budget  device bytes the context may hold (0 = 80 % of free memory).
@@ -77,8 +77,7 @@ typedef struct {
     int32_t seed_dist;
     int32_t tol_radius;
     int32_t min_grains;
-    int32_t cell_xy;
-    int32_t cell_z;
+    int32_t cell[3];
     int32_t device;
     uint32_t flags;
     uint64_t hbm_budget;

@@ -23,8 +23,9 @@ using namespace emt;
 namespace {
 
 constexpr uint32_t kKnownFlags = EMT_F_STATS | EMT_F_FP64_FIT_ALWAYS | EMT_F_DEVICE_PTRS;
-constexpr int kDefaultCellXY = 750;  // 7.5 um, the paper's 32-pixel hash cell
-constexpr int kDefaultCellZ = 500;
+// Default cell edges (units): short along x, where a cell row is one
+// contiguous run, and about the paper's 7.5 um hash cell across it.
+constexpr int kDefaultCell[3] = {250, 750, 500};
 constexpr int kMaxAttempts = 4;
 // seeds of one call are indexed by uint32 and scanned in uint32
 constexpr unsigned long long kSeedCapMax = (1ull << 31) - 1;
@@ -77,12 +78,12 @@ int check_config(const emt_config *c) {
     if (!c) return EMT_EINVAL;
     if (c->abi_version != EMT_ABI_VERSION) return EMT_EINVAL;
     if ((c->flags & ~kKnownFlags) != 0) return EMT_EINVAL;
-    if (c->cell_xy < 0 || c->cell_z < 0) return EMT_EINVAL;
+    if (c->cell[0] < 0 || c->cell[1] < 0 || c->cell[2] < 0) return EMT_EINVAL;
     if (c->device < 0) return EMT_EINVAL;
     if (c->seed_dist < 1 || c->seed_dist > kRMax) return EMT_ERANGE;
     if (c->tol_radius < 0 || c->tol_radius >= c->seed_dist) return EMT_ERANGE;
     if (c->min_grains < 2 || (uint32_t)c->min_grains >= kNMax) return EMT_ERANGE;
-    if (c->cell_xy > kSpanMax || c->cell_z > kSpanMax) return EMT_ERANGE;
+    if (c->cell[0] > kSpanMax || c->cell[1] > kSpanMax || c->cell[2] > kSpanMax) return EMT_ERANGE;
     return EMT_OK;
 }
 
@@ -401,8 +402,7 @@ void emt_default_config(emt_config *cfg) {
     cfg->seed_dist = 2500;
     cfg->tol_radius = 50;
     cfg->min_grains = 8;
-    cfg->cell_xy = 0;
-    cfg->cell_z = 0;
+    cfg->cell[0] = cfg->cell[1] = cfg->cell[2] = 0;
     cfg->device = 0;
     cfg->flags = 0;
     cfg->hbm_budget = 0;
@@ -445,9 +445,7 @@ int emt_create(const emt_config *cfg, emt_ctx **out) {
     ctx->P.r = cfg->tol_radius;
     ctx->P.n_min = cfg->min_grains;
     ctx->P.count_lanes = 1;
-    ctx->P.cell_req[0] = cfg->cell_xy ? cfg->cell_xy : kDefaultCellXY;
-    ctx->P.cell_req[1] = cfg->cell_xy ? cfg->cell_xy : kDefaultCellXY;
-    ctx->P.cell_req[2] = cfg->cell_z ? cfg->cell_z : kDefaultCellZ;
+    for (int m = 0; m < 3; ++m) ctx->P.cell_req[m] = cfg->cell[m] ? cfg->cell[m] : kDefaultCell[m];
     ctx->P.flags = cfg->flags;
     // Tuning hooks: cell edges "x,y,z" in units, and lanes per seed line.
     if (const char *e = std::getenv("EMT_CELL")) {

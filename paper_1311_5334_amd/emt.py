@@ -26,7 +26,7 @@ EXPORTS = ("emt_default_config", "emt_validate", "emt_create", "emt_track_views"
 class EmtConfig(C.Structure):
     _fields_ = [("abi_version", C.c_uint32), ("seed_dist", C.c_int32),
                 ("tol_radius", C.c_int32), ("min_grains", C.c_int32),
-                ("cell_xy", C.c_int32), ("cell_z", C.c_int32), ("device", C.c_int32),
+                ("cell", C.c_int32 * 3), ("device", C.c_int32),
                 ("flags", C.c_uint32), ("hbm_budget", C.c_uint64), ("stream", C.c_void_p)]
 
 
@@ -113,7 +113,10 @@ def emt_default_config(**overrides) -> EmtConfig:
     cfg = EmtConfig()
     load().emt_default_config(C.byref(cfg))
     for k, v in overrides.items():
-        setattr(cfg, k, v)
+        if k == "cell":
+            cfg.cell = (C.c_int32 * 3)(*v)
+        else:
+            setattr(cfg, k, v)
     return cfg
 
 

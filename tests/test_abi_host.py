@@ -87,14 +87,13 @@ def test_defaults_and_strerror(emt):
 
 
 @pytest.mark.parametrize("field,value,rc", [
-    ("abi_version", 7, -1), ("flags", 0x100, -1), ("cell_xy", -5, -1), ("device", -1, -1),
+    ("abi_version", 7, -1), ("flags", 0x100, -1), ("cell", (-5, 0, 0), -1), ("device", -1, -1),
     ("seed_dist", 0, -2), ("seed_dist", 4097, -2), ("tol_radius", -1, -2),
     ("tol_radius", 2500, -2), ("min_grains", 1, -2), ("min_grains", 1 << 20, -2),
-    ("cell_z", (1 << 18) + 1, -2),
+    ("cell", (0, 0, (1 << 18) + 1), -2),
 ])
 def test_validate_rejects_bad_config(emt, field, value, rc):
-    cfg = emt.emt_default_config()
-    setattr(cfg, field, value)
+    cfg = emt.emt_default_config(**{field: value})
     assert emt.emt_validate(cfg) == rc
 
 

@@ -184,8 +184,9 @@ def test_overflow_retry_gives_same_result(emt, tracker, monkeypatch):
 def test_cell_geometry_never_changes_results(emt, oracle_mod):
     v = synth.make_c1(18)
     ref = oracle_mod.track_view(v.xyz)
-    for cxy, cz in ((150, 170), (500, 500), (1200, 300), (3000, 5000), (97, 61)):
-        with emt.Tracker(device=0, cell_xy=cxy, cell_z=cz) as t:
+    for cell in ((150, 150, 170), (500, 500, 500), (1200, 1200, 300), (3000, 3000, 5000),
+                 (97, 97, 61), (750, 750, 170), (100, 900, 400)):
+        with emt.Tracker(device=0, cell=cell) as t:
             assert_view_parity(v.xyz, run1(t, v.xyz), ref)
 
 
