@@ -60,16 +60,25 @@ struct emt_ctx {
     int32_t *h_xyz = nullptr;
     size_t h_xyz_cap = 0;
     ViewGrid *h_grids = nullptr;
-    unsigned long long *h_view_seeds = nullptr;
-    uint32_t *h_view_cand = nullptr, *h_view_ntr = nullptr, *h_view_tr_off = nullptr;
     uint32_t h_views_cap = 0;
-    Counters *h_cnt = nullptr;
-    emt_track *h_tracks = nullptr;
-    size_t h_tracks_cap = 0;
-    uint32_t *h_grains = nullptr;
-    size_t h_grains_cap = 0;
+    // results, in mapped pinned memory written by the device
+    HostOut h{};                  // host addresses
+    size_t cap_out_views = 0, cap_out_cnt = 0, cap_out_tracks = 0, cap_out_grains = 0;
+    size_t cap_vs = 0, cap_vc = 0, cap_vn = 0, cap_vo = 0, cap_ve = 0;
 
     emt_call_stats last{};
+
+    // captured launch sequences, keyed by capacities and buffer generation
+    struct GraphEntry {
+        Caps caps;
+        unsigned gen;
+        int stage;  // -1: the whole sequence
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    unsigned gen = 0;        // bumped whenever a device buffer moves
+    bool use_graphs = true;
+    BatchDesc *h_desc = nullptr;
 };
 
 namespace {
@@ -142,6 +151,7 @@ int arena(emt_ctx *ctx, DevArena &a, size_t bytes) {
         a.bytes = 0;
     }
     if (ctx->held + bytes > ctx->budget) return EMT_ENOMEM;
+    ctx->gen++;
     if (hipMalloc(&a.p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return EMT_ENOMEM;
@@ -167,6 +177,34 @@ int pinned(emt_ctx *ctx, T *&p, size_t &cap, size_t n) {
     if (hipHostMalloc((void **)&p, want * sizeof(T), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         return EMT_ENOMEM;
+    }
+    cap = want;
+    return EMT_OK;
+}
+
+// Mapped pinned host memory the device writes results into.
+template <class T>
+int mapped(emt_ctx *ctx, T *&host, T *&dev, size_t &cap, size_t n) {
+    if (cap >= n && host) return EMT_OK;
+    if (host) {
+        if (hipHostFree(host) != hipSuccess) {
+            ctx->poisoned = true;
+            return EMT_EDEVICE;
+        }
+        host = nullptr;
+        dev = nullptr;
+        cap = 0;
+    }
+    ctx->gen++;
+    size_t want = std::max<size_t>(n, 64);
+    if (hipHostMalloc((void **)&host, want * sizeof(T), hipHostMallocMapped) != hipSuccess) {
+        (void)hipGetLastError();
+        host = nullptr;
+        return EMT_ENOMEM;
+    }
+    if (hipHostGetDevicePointer((void **)&dev, host, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return EMT_EDEVICE;
     }
     cap = want;
     return EMT_OK;
@@ -261,7 +299,7 @@ int ensure(emt_ctx *ctx, Caps &c) {
         const size_t n = std::max<uint32_t>(c.n_views, 64);
         const size_t b = bytes_of<ViewGrid>(n) + bytes_of<unsigned long long>(n) +
                          4 * bytes_of<uint32_t>(n + 1) + bytes_of<Counters>(1) +
-                         bytes_of<uint32_t>((size_t)max_merge_rounds());
+                         bytes_of<uint32_t>((size_t)max_merge_rounds()) + bytes_of<BatchDesc>(1);
         if ((rc = arena(ctx, ctx->view_buf, b))) return rc;
         char *p = (char *)ctx->view_buf.p;
         d.grids = carve<ViewGrid>(p, n);
@@ -272,31 +310,33 @@ int ensure(emt_ctx *ctx, Caps &c) {
         d.view_cursor = carve<uint32_t>(p, n + 1);
         d.cnt = carve<Counters>(p, 1);
         d.undecided = carve<uint32_t>(p, (size_t)max_merge_rounds());
+        d.desc = carve<BatchDesc>(p, 1);
         ctx->cap_views = (uint32_t)n;
-        // matching pinned host arrays
+        // matching pinned staging of the view table
         size_t cap = 0;
         if (ctx->h_grids) {
             (void)hipHostFree(ctx->h_grids);
-            (void)hipHostFree(ctx->h_view_seeds);
-            (void)hipHostFree(ctx->h_view_cand);
-            (void)hipHostFree(ctx->h_view_ntr);
-            (void)hipHostFree(ctx->h_view_tr_off);
             ctx->h_grids = nullptr;
         }
         if ((rc = pinned(ctx, ctx->h_grids, cap, n))) return rc;
-        cap = 0;
-        if ((rc = pinned(ctx, ctx->h_view_seeds, cap, n))) return rc;
-        cap = 0;
-        if ((rc = pinned(ctx, ctx->h_view_cand, cap, n + 1))) return rc;
-        cap = 0;
-        if ((rc = pinned(ctx, ctx->h_view_ntr, cap, n + 1))) return rc;
-        cap = 0;
-        if ((rc = pinned(ctx, ctx->h_view_tr_off, cap, n + 1))) return rc;
         ctx->h_views_cap = (uint32_t)n;
     }
-    if (!ctx->h_cnt) {
+    if (!ctx->h_desc) {
         size_t cap = 0;
-        if ((rc = pinned(ctx, ctx->h_cnt, cap, 1))) return rc;
+        if ((rc = pinned(ctx, ctx->h_desc, cap, 1))) return rc;
+    }
+    {
+        const size_t nv = ctx->cap_views + 1;
+        HostOut &h = ctx->h;
+        HostOut &o = d.out;
+        if ((rc = mapped(ctx, h.cnt, o.cnt, ctx->cap_out_cnt, 1))) return rc;
+        if ((rc = mapped(ctx, h.view_seeds, o.view_seeds, ctx->cap_vs, nv))) return rc;
+        if ((rc = mapped(ctx, h.view_cand, o.view_cand, ctx->cap_vc, nv))) return rc;
+        if ((rc = mapped(ctx, h.view_ntr, o.view_ntr, ctx->cap_vn, nv))) return rc;
+        if ((rc = mapped(ctx, h.view_tr_off, o.view_tr_off, ctx->cap_vo, nv))) return rc;
+        if ((rc = mapped(ctx, h.view_err, o.view_err, ctx->cap_ve, nv))) return rc;
+        if ((rc = mapped(ctx, h.tracks, o.tracks, ctx->cap_out_tracks, c.cand_cap))) return rc;
+        if ((rc = mapped(ctx, h.grains, o.grains, ctx->cap_out_grains, c.mem_cap))) return rc;
     }
     return EMT_OK;
 }
@@ -311,84 +351,157 @@ uint32_t clamp_u32(double x) {
     return (uint32_t)x;
 }
 
+// The kernel sequence of one batch, in stages: 0 bin, 1 seeds, 2 count,
+// 3 candidates and members, 4 merge, 5 fit, 6 results to the host; -1 runs
+// them all.
+constexpr int kStages = 7;
+
+void launch_stage(emt_ctx *ctx, const DevPtrs &run, const Caps &c, hipStream_t s, int stage) {
+    switch (stage) {
+        case 0:
+            launch_prepare(run, c, ctx->P, s);
+            launch_bin(run, c, ctx->P, s);
+            break;
+        case 1:
+            launch_seeds(run, c, ctx->P, s);
+            break;
+        case 2:
+            launch_count(run, c, ctx->P, s);
+            break;
+        case 3:
+            launch_candidates(run, c, ctx->P, s);
+            launch_members(run, c, ctx->P, s);
+            break;
+        case 4:
+            launch_merge_init(run, c, ctx->P, s);
+            launch_merge(run, c, ctx->P, s);
+            break;
+        case 5:
+            launch_fit(run, c, ctx->P, s);
+            break;
+        default:
+            launch_copy_out(run, c, ctx->P, s);
+            break;
+    }
+}
+
+void launch_stages(emt_ctx *ctx, const Caps &c, hipStream_t s, int stage) {
+    if (stage >= 0) {
+        launch_stage(ctx, ctx->d, c, s, stage);
+        return;
+    }
+    for (int k = 0; k < kStages; ++k) launch_stage(ctx, ctx->d, c, s, k);
+}
+
+bool same_caps(const Caps &a, const Caps &b) {
+    return a.n_total == b.n_total && a.n_views == b.n_views && a.n_cells == b.n_cells &&
+           a.max_view_n == b.max_view_n && a.seed_cap == b.seed_cap &&
+           a.cand_cap == b.cand_cap && a.mem_cap == b.mem_cap;
+}
+
+void drop_graphs(emt_ctx *ctx) {
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+    ctx->graphs.clear();
+}
+
+// Run one stage (or all, stage -1): replay the graph captured for these
+// capacities, capturing it first if needed; eager launches if graphs are off
+// or capture fails.
+int launch_graph(emt_ctx *ctx, const Caps &c, int stage) {
+    hipStream_t s = ctx->stream;
+    if (ctx->use_graphs) {
+        for (auto &g : ctx->graphs) {
+            if (g.gen == ctx->gen && g.stage == stage && same_caps(g.caps, c)) {
+                HIP_OK(hipGraphLaunch(g.exec, s));
+                return EMT_OK;
+            }
+        }
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            launch_stages(ctx, c, s, stage);
+            ok = hipStreamEndCapture(s, &graph) == hipSuccess && graph != nullptr;
+        }
+        if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ok) {
+            if (ctx->graphs.size() >= 16) {
+                (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+                ctx->graphs.erase(ctx->graphs.begin());
+            }
+            ctx->graphs.push_back({c, ctx->gen, stage, exec});
+            HIP_OK(hipGraphLaunch(exec, s));
+            return EMT_OK;
+        }
+        // capture is not available here: run eagerly from now on
+        (void)hipGetLastError();
+        ctx->use_graphs = false;
+    }
+    launch_stages(ctx, c, s, stage);
+    return hipGetLastError() == hipSuccess ? EMT_OK : EMT_EDEVICE;
+}
+
+// The whole kernel sequence. With EMT_F_STATS each stage is its own graph
+// and the timing events are recorded between them.
+int launch_sequence(emt_ctx *ctx, const Caps &c) {
+    if (!(ctx->cfg.flags & EMT_F_STATS)) return launch_graph(ctx, c, -1);
+    for (int k = 0; k < kStages; ++k) {
+        int rc = launch_graph(ctx, c, k);
+        if (rc) return rc;
+        record(ctx, k + 2);  // events 2..8 close stages bin..out
+    }
+    return EMT_OK;
+}
+
 // One attempt at the whole batch. Returns EMT_OK, EMT_EOVERFLOW (caps too
-// small: ctx->h_cnt holds the needs) or an error.
+// small: ctx->h.cnt holds the needs) or an error.
 int run_once(emt_ctx *ctx, const emt_view_in *views, uint32_t nv, const Caps &c,
              bool *overflow) {
     DevPtrs &d = ctx->d;
     hipStream_t s = ctx->stream;
     *overflow = false;
     record(ctx, 0);
-    // stage the grains
+    // stage the grains into the packed buffer
     const bool dev = (ctx->cfg.flags & EMT_F_DEVICE_PTRS) != 0;
-    DevPtrs run = d;
-    if (dev && nv == 1) {
-        run.xyz = views[0].xyz;
-    } else if (dev) {
+    if (dev) {
         for (uint32_t v = 0; v < nv; ++v) {
             if (!views[v].n_grains) continue;
             HIP_OK(hipMemcpyAsync((void *)(d.xyz + 3 * (size_t)ctx->h_grids[v].grain_off),
                                   views[v].xyz, 12 * (size_t)views[v].n_grains,
                                   hipMemcpyDeviceToDevice, s));
         }
-    } else {
-        HIP_OK(hipMemcpyAsync((void *)d.xyz, ctx->h_xyz, 12 * (size_t)c.n_total,
+    } else if (ctx->h_desc->n_total) {
+        HIP_OK(hipMemcpyAsync((void *)d.xyz, ctx->h_xyz, 12 * (size_t)ctx->h_desc->n_total,
                               hipMemcpyHostToDevice, s));
     }
     HIP_OK(hipMemcpyAsync(d.grids, ctx->h_grids, sizeof(ViewGrid) * nv, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync((void *)d.desc, ctx->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice, s));
     record(ctx, 1);
-    launch_prepare(run, c, ctx->P, s);
-    launch_bin(run, c, ctx->P, s);
-    record(ctx, 2);
-    launch_seeds(run, c, ctx->P, s);
-    record(ctx, 3);
-    launch_count(run, c, ctx->P, s);
-    record(ctx, 4);
-    launch_candidates(run, c, ctx->P, s);
-    launch_members(run, c, ctx->P, s);
-    record(ctx, 5);
-    launch_merge_init(run, c, ctx->P, s);
-    launch_merge(run, c, ctx->P, s);
-    record(ctx, 6);
-    launch_fit(run, c, ctx->P, s);
-    record(ctx, 7);
-    HIP_OK(hipMemcpyAsync(ctx->h_cnt, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipMemcpyAsync(ctx->h_view_seeds, d.view_seeds, sizeof(unsigned long long) * nv,
-                          hipMemcpyDeviceToHost, s));
-    HIP_OK(hipMemcpyAsync(ctx->h_view_cand, d.view_cand, sizeof(uint32_t) * nv,
-                          hipMemcpyDeviceToHost, s));
-    HIP_OK(hipMemcpyAsync(ctx->h_view_ntr, d.view_ntr, sizeof(uint32_t) * nv,
-                          hipMemcpyDeviceToHost, s));
-    HIP_OK(hipMemcpyAsync(ctx->h_view_tr_off, d.view_tr_off, sizeof(uint32_t) * (nv + 1),
-                          hipMemcpyDeviceToHost, s));
-    HIP_OK(hipMemcpyAsync(ctx->h_grids, d.grids, sizeof(ViewGrid) * nv, hipMemcpyDeviceToHost, s));
+    int rc = launch_sequence(ctx, c);
+    if (rc) {
+        ctx->poisoned = true;
+        return rc;
+    }
+    if (!(ctx->cfg.flags & EMT_F_STATS)) record(ctx, 8);
     HIP_OK(hipStreamSynchronize(s));
-    {
-        const Counters &h = *ctx->h_cnt;
-        if (h.n_seeds > c.seed_cap || h.n_cand > c.cand_cap || h.n_members > c.mem_cap) {
-            *overflow = true;
-            return EMT_EOVERFLOW;
-        }
-        if (h.err & 4u) {
-            ctx->poisoned = true;
-            return EMT_EDEVICE;
-        }
+    const Counters &h = *ctx->h.cnt;
+    if (h.n_seeds > c.seed_cap || h.n_cand > c.cand_cap || h.n_members > c.mem_cap) {
+        *overflow = true;
+        return EMT_EOVERFLOW;
     }
-    const uint32_t nt = ctx->h_cnt->n_acc, ng = ctx->h_cnt->n_track_grains;
-    int rc;
-    if ((rc = pinned(ctx, ctx->h_tracks, ctx->h_tracks_cap, nt))) return rc;
-    if ((rc = pinned(ctx, ctx->h_grains, ctx->h_grains_cap, ng))) return rc;
-    if (nt) {
-        HIP_OK(hipMemcpyAsync(ctx->h_tracks, d.tracks, sizeof(emt_track) * nt,
-                              hipMemcpyDeviceToHost, s));
+    if (h.err & 4u) {
+        ctx->poisoned = true;
+        return EMT_EDEVICE;
     }
-    if (ng) {
-        HIP_OK(hipMemcpyAsync(ctx->h_grains, d.out_grains, sizeof(uint32_t) * ng,
-                              hipMemcpyDeviceToHost, s));
-    }
-    record(ctx, 8);
-    HIP_OK(hipStreamSynchronize(s));
     return EMT_OK;
+}
+
+// Capacity bucket: the next power of two, at least lo.
+uint32_t bucket(uint64_t n, uint32_t lo) {
+    uint64_t b = lo;
+    while (b < n) b <<= 1;
+    return (uint32_t)std::min<uint64_t>(b, 0x80000000ull);
 }
 
 }  // namespace
@@ -458,6 +571,7 @@ int emt_create(const emt_config *cfg, emt_ctx **out) {
         const int k = std::atoi(e);
         ctx->P.count_lanes = (k >= 4) ? 4 : (k >= 2 ? 2 : 1);
     }
+    if (const char *e = std::getenv("EMT_NO_GRAPH")) ctx->use_graphs = (std::atoi(e) == 0);
     // Test hook: start from tiny capacities so the first call overflows and
     // the retry path runs.
     if (const char *e = std::getenv("EMT_INITIAL_CAPS")) {
@@ -492,7 +606,18 @@ int emt_create(const emt_config *cfg, emt_ctx **out) {
     return EMT_OK;
 }
 
+static int track_views_impl(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views,
+                            emt_view_out *out);
+
 int emt_track_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views, emt_view_out *out) {
+    const int rc = track_views_impl(ctx, views, n_views, out);
+    // return codes carry every failure: leave no sticky HIP error behind
+    (void)hipGetLastError();
+    return rc;
+}
+
+static int track_views_impl(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views,
+                            emt_view_out *out) {
     if (!ctx) return EMT_EINVAL;
     if (ctx->poisoned) return EMT_EDEVICE;
     if (n_views > 0 && !out) return EMT_EINVAL;
@@ -503,9 +628,7 @@ int emt_track_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views, em
         ctx->poisoned = true;
         return EMT_EDEVICE;
     }
-    // batch geometry
-    Caps c{};
-    c.n_views = n_views;
+    // batch sizes (to the device) and capacity buckets (launch shapes)
     unsigned long long n_total = 0, n_cells = 0;
     uint32_t max_n = 0;
     for (uint32_t v = 0; v < n_views; ++v) {
@@ -513,23 +636,28 @@ int emt_track_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views, em
         n_cells += 4ull * views[v].n_grains + 4096 + 1;
         max_n = std::max(max_n, views[v].n_grains);
     }
-    if (n_cells >= (1ull << 31)) return EMT_ERANGE;
-    c.n_total = (uint32_t)n_total;
-    c.n_cells = (uint32_t)n_cells;
-    c.max_view_n = max_n;
+    Caps c{};
+    c.n_total = bucket(n_total, 1024);
+    c.n_views = bucket(n_views, 1);
+    const unsigned long long cells_cap = 4ull * c.n_total + 4097ull * c.n_views;
+    if (cells_cap >= (1ull << 31)) return EMT_ERANGE;
+    c.n_cells = (uint32_t)cells_cap;
+    c.max_view_n = std::min(c.n_total, bucket(max_n, 64));
     c.seed_cap = std::min<unsigned long long>(
         kSeedCapMax, std::max<unsigned long long>(
-                         4096, (unsigned long long)(ctx->seeds_per_grain * (double)n_total)));
-    c.cand_cap = clamp_u32(ctx->cand_per_grain * (double)n_total);
+                         4096, (unsigned long long)(ctx->seeds_per_grain * (double)c.n_total)));
+    c.cand_cap = clamp_u32(ctx->cand_per_grain * (double)c.n_total);
     c.mem_cap = clamp_u32(ctx->mem_per_cand * (double)c.cand_cap);
 
     // ensure the view tables exist before filling pinned staging
     if ((rc = ensure(ctx, c))) return rc;
+    ctx->h_desc->n_total = (uint32_t)n_total;
+    ctx->h_desc->n_views = n_views;
+    ctx->h_desc->n_cells = (uint32_t)n_cells;
+    ctx->h_desc->n_cells_m1 = (uint32_t)n_cells - 1u;
     if (!(ctx->cfg.flags & EMT_F_DEVICE_PTRS)) {
-        if ((rc = pinned(ctx, ctx->h_xyz, ctx->h_xyz_cap, 3 * (size_t)std::max<uint32_t>(c.n_total, 1))))
+        if ((rc = pinned(ctx, ctx->h_xyz, ctx->h_xyz_cap, 3 * (size_t)std::max<unsigned long long>(n_total, 1))))
             return rc;
-    }
-    if (!(ctx->cfg.flags & EMT_F_DEVICE_PTRS)) {
         uint32_t goff = 0;
         for (uint32_t v = 0; v < n_views; ++v) {
             if (views[v].n_grains)
@@ -564,18 +692,18 @@ int emt_track_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views, em
         if (!overflow) return rc;
         if (attempt + 1 >= kMaxAttempts) return EMT_EOVERFLOW;
         ++retries;
-        const Counters h = *ctx->h_cnt;
+        const Counters h = *ctx->h.cnt;
         // the counters are exact for the stage that overflowed; later stages
         // are sized from the per-grain and per-candidate ratios
         if (h.n_seeds > c.seed_cap) {
             if (h.n_seeds >= kSeedCapMax) return EMT_EOVERFLOW;
             c.seed_cap = std::min<unsigned long long>(kSeedCapMax,
                                                       h.n_seeds + h.n_seeds / 8 + 1024);
-            ctx->seeds_per_grain = std::max(ctx->seeds_per_grain, 1.125 * (double)h.n_seeds / std::max(1.0, (double)n_total));
+            ctx->seeds_per_grain = std::max(ctx->seeds_per_grain, 1.125 * (double)h.n_seeds / std::max(1.0, (double)c.n_total));
         }
         if (h.n_cand > c.cand_cap) {
             c.cand_cap = clamp_u32((double)h.n_cand * 1.125 + 1024);
-            ctx->cand_per_grain = std::max(ctx->cand_per_grain, 1.125 * (double)h.n_cand / std::max(1.0, (double)n_total));
+            ctx->cand_per_grain = std::max(ctx->cand_per_grain, 1.125 * (double)h.n_cand / std::max(1.0, (double)c.n_total));
         }
         if (h.n_members > c.mem_cap || h.n_cand > c.cand_cap) {
             const double per = h.n_cand ? (double)h.n_members / (double)h.n_cand : ctx->mem_per_cand;
@@ -587,32 +715,32 @@ int emt_track_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views, em
 
     // device-side rejections (span of device-resident views)
     for (uint32_t v = 0; v < n_views; ++v)
-        if (ctx->h_grids[v].err) return EMT_ERANGE;
-    if (ctx->h_cnt->err & 2u) {
+        if (ctx->h.view_err[v]) return EMT_ERANGE;
+    if (ctx->h.cnt->err & 2u) {
         // member lists disagreed with the counts: an internal fault
         ctx->poisoned = true;
         return EMT_EDEVICE;
     }
 
     // outputs: per-view slices of the track and grain arrays
-    const Counters &h = *ctx->h_cnt;
+    const Counters &h = *ctx->h.cnt;
     for (uint32_t v = 0; v < n_views; ++v) {
         emt_view_out &o = out[v];
-        const uint32_t t0 = ctx->h_view_tr_off[v], nt = ctx->h_view_ntr[v];
+        const uint32_t t0 = ctx->h.view_tr_off[v], nt = ctx->h.view_ntr[v];
         o.view_id = views[v].view_id;
         o.n_tracks = nt;
-        o.tracks = ctx->h_tracks + t0;
-        const uint32_t g0 = nt ? ctx->h_tracks[t0].grain_offset : 0;
+        o.tracks = ctx->h.tracks + t0;
+        const uint32_t g0 = nt ? ctx->h.tracks[t0].grain_offset : 0;
         uint32_t ng = 0;
         for (uint32_t t = 0; t < nt; ++t) {
-            emt_track &tr = ctx->h_tracks[t0 + t];
+            emt_track &tr = ctx->h.tracks[t0 + t];
             tr.grain_offset -= g0;
             ng += tr.n_grains;
         }
         o.n_track_grains = ng;
-        o.grains = ctx->h_grains + g0;
-        o.stats.n_seeds = ctx->h_view_seeds[v];
-        o.stats.n_candidates = ctx->h_view_cand[v];
+        o.grains = ctx->h.grains + g0;
+        o.stats.n_seeds = ctx->h.view_seeds[v];
+        o.stats.n_candidates = ctx->h.view_cand[v];
         o.stats.n_tracks = nt;
     }
     emt_call_stats &st = ctx->last;
@@ -649,19 +777,21 @@ void emt_destroy(emt_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->cfg.device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    drop_graphs(ctx);
     DevArena *arenas[] = {&ctx->grain_buf, &ctx->cell_buf, &ctx->seed_buf, &ctx->cand_buf,
                           &ctx->mem_buf, &ctx->view_buf, &ctx->misc_buf};
     for (DevArena *a : arenas)
         if (a->p) (void)hipFree(a->p);
-    void *hosts[] = {ctx->h_xyz, ctx->h_grids, ctx->h_view_seeds, ctx->h_view_cand,
-                     ctx->h_view_ntr, ctx->h_view_tr_off, ctx->h_cnt,
-                     ctx->h_tracks, ctx->h_grains};
+    void *hosts[] = {ctx->h_xyz, ctx->h_grids, ctx->h_desc, ctx->h.cnt, ctx->h.view_seeds,
+                     ctx->h.view_cand, ctx->h.view_ntr, ctx->h.view_tr_off, ctx->h.view_err,
+                     ctx->h.tracks, ctx->h.grains};
     for (void *p : hosts)
         if (p) (void)hipHostFree(p);
     for (int i = 0; i <= EMT_N_STAGES; ++i)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
+    (void)hipGetLastError();
 }
 
 }  // extern "C"

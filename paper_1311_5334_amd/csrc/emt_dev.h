@@ -31,6 +31,15 @@ struct ViewGrid {
     int32_t pad[3];
 };
 
+// Sizes of the batch in flight, in device memory so that one captured launch
+// sequence serves every batch within its capacities.
+struct BatchDesc {
+    uint32_t n_total;     // grains
+    uint32_t n_views;
+    uint32_t n_cells;     // cell table entries in use
+    uint32_t n_cells_m1;  // n_cells - 1 (scan length of the cell table)
+};
+
 struct Params {
     int32_t R, r, n_min, count_lanes;
     int32_t cell_req[3];
@@ -70,6 +79,19 @@ __host__ __device__ inline unsigned long long cand_key(uint32_t n, uint32_t i,
 }
 
 enum : uint8_t { kUndecided = 0, kAccepted = 1, kRejected = 2 };
+
+// Results, written by the last kernel straight into mapped pinned host
+// memory (device-side addresses of host buffers).
+struct HostOut {
+    Counters *cnt;
+    unsigned long long *view_seeds;
+    uint32_t *view_cand;
+    uint32_t *view_ntr;
+    uint32_t *view_tr_off;
+    int32_t *view_err;
+    emt_track *tracks;     // cand_cap
+    uint32_t *grains;      // mem_cap
+};
 
 // All device buffers of one call, as raw pointers.
 struct DevPtrs {
@@ -115,13 +137,17 @@ struct DevPtrs {
     uint32_t *view_cursor;  // V
     uint32_t *scan_part;  // scan scratch
     Counters *cnt;
+    const BatchDesc *desc;
+    HostOut out;
 };
 
+// Capacities a launch sequence is built for (the actual sizes are in
+// BatchDesc and never exceed these).
 struct Caps {
-    uint32_t n_total;         // grains in the batch
+    uint32_t n_total;         // grains
     uint32_t n_views;
-    uint32_t n_cells;         // C
-    uint32_t max_view_n;
+    uint32_t n_cells;         // cell table entries
+    uint32_t max_view_n;      // grains of the largest view
     unsigned long long seed_cap;
     uint32_t cand_cap;
     uint32_t mem_cap;
@@ -137,6 +163,7 @@ void launch_members(const DevPtrs &d, const Caps &c, const Params &P, hipStream_
 void launch_merge_init(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
 void launch_merge(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
 void launch_fit(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
+void launch_copy_out(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
 
 size_t scan_scratch_words(uint32_t n_cap);
 int max_merge_rounds();

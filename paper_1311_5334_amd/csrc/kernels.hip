@@ -184,9 +184,10 @@ void scan_excl(const uint32_t *in, const uint32_t *n_dev, uint32_t n_cap, uint32
 
 __global__ void __launch_bounds__(kBlock) k_zero(Counters *cnt, unsigned long long *view_seeds,
                                                  uint32_t *view_cand, uint32_t *view_ntr,
-                                                 uint32_t *view_cursor, uint32_t n_views,
-                                                 uint32_t *cell_count, uint32_t n_cells) {
+                                                 uint32_t *view_cursor, uint32_t *cell_count,
+                                                 const BatchDesc *desc) {
     const uint32_t tid = grid_tid();
+    const uint32_t n_views = desc->n_views, n_cells = desc->n_cells;
     if (tid == 0) {
         Counters z = {};
         *cnt = z;
@@ -202,8 +203,9 @@ __global__ void __launch_bounds__(kBlock) k_zero(Counters *cnt, unsigned long lo
 
 // Bounding box of every view (grid origin) and the view index of each grain.
 __global__ void __launch_bounds__(kBlock) k_bbox(const int32_t *xyz, ViewGrid *grids,
-                                                 uint32_t *view_of) {
+                                                 uint32_t *view_of, const BatchDesc *desc) {
     const uint32_t v = blockIdx.y;
+    if (v >= desc->n_views) return;
     const uint32_t off = grids[v].grain_off, n = grids[v].n;
     int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
     int hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
@@ -234,9 +236,9 @@ __global__ void __launch_bounds__(kBlock) k_bbox(const int32_t *xyz, ViewGrid *g
 // most cell_cap cells. A view whose span exceeds the limit is marked: its
 // grains still go through the binning (into one cell, so every later view
 // keeps its place in the sorted arrays) but it produces no seeds.
-__global__ void k_grid(ViewGrid *grids, uint32_t n_views, Params P) {
+__global__ void k_grid(ViewGrid *grids, const BatchDesc *desc, Params P) {
     const uint32_t v = grid_tid();
-    if (v >= n_views) return;
+    if (v >= desc->n_views) return;
     ViewGrid G = grids[v];
     long long span[3];
     for (int m = 0; m < 3; ++m) {
@@ -280,8 +282,9 @@ __device__ __forceinline__ uint32_t cell_index(const ViewGrid &G, int x, int y, 
 
 __global__ void __launch_bounds__(kBlock) k_hist(const int32_t *xyz, const ViewGrid *grids,
                                                  uint32_t *cell_of, uint32_t *rank,
-                                                 uint32_t *cell_count) {
+                                                 uint32_t *cell_count, const BatchDesc *desc) {
     const uint32_t v = blockIdx.y;
+    if (v >= desc->n_views) return;
     const ViewGrid G = grids[v];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < G.n; i += gridDim.x * blockDim.x) {
         const size_t g = (size_t)G.grain_off + i;
@@ -295,8 +298,10 @@ __global__ void __launch_bounds__(kBlock) k_hist(const int32_t *xyz, const ViewG
 // the input index within the view.
 __global__ void __launch_bounds__(kBlock) k_scatter(const int32_t *xyz, const ViewGrid *grids,
                                                     const uint32_t *cell_of, const uint32_t *rank,
-                                                    const uint32_t *cell_start, int4 *sg) {
+                                                    const uint32_t *cell_start, int4 *sg,
+                                                    const BatchDesc *desc) {
     const uint32_t v = blockIdx.y;
+    if (v >= desc->n_views) return;
     const ViewGrid G = grids[v];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < G.n; i += gridDim.x * blockDim.x) {
         const size_t g = (size_t)G.grain_off + i;
@@ -517,7 +522,8 @@ __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
     const uint32_t gw = grid_tid() >> 6, nw = grid_threads() >> 6;
     const int R1 = P.R - 1;
     const int R2 = P.R * P.R;
-    for (uint32_t p = gw; p < c.n_total; p += nw) {
+    const uint32_t n_total = d.desc->n_total;
+    for (uint32_t p = gw; p < n_total; p += nw) {
         const uint32_t v = d.view_of[p];
         const ViewGrid *G = &d.grids[v];
         uint32_t base = kWrite ? d.seed_off[p] : 0u;
@@ -579,7 +585,7 @@ __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
 __global__ void k_seed_total(DevPtrs d, Caps c) {
     if (grid_tid() != 0) return;
     // the scan total counts every seed; it wraps only above 2^32 - 1 per call
-    d.cnt->n_seeds = d.seed_off[c.n_total];
+    d.cnt->n_seeds = d.seed_off[d.desc->n_total];
 }
 
 // ------------------------------------------------------- count / members
@@ -1050,7 +1056,7 @@ __global__ void __launch_bounds__(kBlock) k_cand_scatter(DevPtrs d, Caps c) {
 // in anchor order, so in seed and in candidate order too).
 __global__ void k_view_counts(DevPtrs d, Caps c) {
     const uint32_t v = grid_tid();
-    if (v >= c.n_views) return;
+    if (v >= d.desc->n_views) return;
     const uint32_t g0 = d.grids[v].grain_off, g1 = g0 + d.grids[v].n;
     const uint32_t ns = min(d.cnt->n_seeds, (uint32_t)c.seed_cap);
     const uint32_t s0 = d.seed_off[g0], s1 = d.seed_off[g1];
@@ -1082,7 +1088,7 @@ __global__ void __launch_bounds__(kBlock) k_cand_n(DevPtrs d, Caps c) {
 // its member entries; decided candidates cost one status read.
 
 constexpr int kMaxRounds = 256;
-constexpr int kWideRounds = 4;  // rounds run grid-wide before the tail kernel
+constexpr int kWideRounds = 6;  // rounds run grid-wide before the tail kernel
 
 __global__ void __launch_bounds__(kBlock) k_merge_init(DevPtrs d, Caps c) {
     const Counters *cn = d.cnt;
@@ -1094,7 +1100,8 @@ __global__ void __launch_bounds__(kBlock) k_merge_init(DevPtrs d, Caps c) {
         d.status[i] = kUndecided;
         d.mcount[i] = 0;
     }
-    for (uint32_t g = grid_tid(); g < c.n_total; g += grid_threads()) {
+    const uint32_t n_total = d.desc->n_total;
+    for (uint32_t g = grid_tid(); g < n_total; g += grid_threads()) {
         d.used[g] = 0;
         d.owner[g] = ~0ull;
     }
@@ -1290,7 +1297,8 @@ __global__ void __launch_bounds__(kBlock) k_collect(DevPtrs d, Caps c) {
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_view_offsets(DevPtrs d, uint32_t n_views) {
+__global__ void __launch_bounds__(kBlock) k_view_offsets(DevPtrs d) {
+    const uint32_t n_views = d.desc->n_views;
     uint32_t carry = 0;
     for (uint32_t base = 0; base < n_views; base += kBlock) {
         const uint32_t i = base + threadIdx.x;
@@ -1535,6 +1543,29 @@ __global__ void __launch_bounds__(kBlock) k_fit(DevPtrs d, Params P) {
     }
 }
 
+// Results to the host: counters, per-view tables, tracks and grains, at the
+// sizes the device knows, into mapped pinned host memory.
+__global__ void __launch_bounds__(kBlock) k_copy_out(DevPtrs d, Caps c) {
+    const uint32_t tid = grid_tid(), nt = grid_threads();
+    const uint32_t nv = d.desc->n_views;
+    const Counters cn = *d.cnt;
+    if (tid == 0) *d.out.cnt = cn;
+    for (uint32_t v = tid; v < nv; v += nt) {
+        d.out.view_seeds[v] = d.view_seeds[v];
+        d.out.view_cand[v] = d.view_cand[v];
+        d.out.view_ntr[v] = d.view_ntr[v];
+        d.out.view_err[v] = d.grids[v].err;
+    }
+    for (uint32_t v = tid; v <= nv; v += nt) d.out.view_tr_off[v] = d.view_tr_off[v];
+    const uint32_t ntr = cn.n_acc <= c.cand_cap ? cn.n_acc : 0u;
+    const uint32_t words = ntr * (uint32_t)(sizeof(emt_track) / 4);
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(d.tracks);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(d.out.tracks);
+    for (uint32_t i = tid; i < words; i += nt) dst[i] = src[i];
+    const uint32_t ng = cn.n_track_grains <= c.mem_cap ? cn.n_track_grains : 0u;
+    for (uint32_t i = tid; i < ng; i += nt) d.out.grains[i] = d.out_grains[i];
+}
+
 uint32_t blocks_for(unsigned long long n, uint32_t max_blocks) {
     unsigned long long b = (n + kBlock - 1) / kBlock;
     if (b < 1) b = 1;
@@ -1549,24 +1580,25 @@ size_t scan_scratch_words(uint32_t n_cap) { return (size_t)n_cap / kScanTile + 2
 
 void launch_prepare(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {
     k_zero<<<blocks_for(c.n_cells, 1024), kBlock, 0, s>>>(d.cnt, d.view_seeds, d.view_cand,
-                                                          d.view_ntr, d.view_cursor, c.n_views,
-                                                          d.cell_count, c.n_cells);
+                                                          d.view_ntr, d.view_cursor, d.cell_count,
+                                                          d.desc);
 }
 
 void launch_bin(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
     const uint32_t bx = blocks_for(c.max_view_n, 64);
     dim3 grid(bx, c.n_views);
-    k_bbox<<<grid, kBlock, 0, s>>>(d.xyz, d.grids, d.view_of);
-    k_grid<<<(c.n_views + 63) / 64, 64, 0, s>>>(d.grids, c.n_views, P);
-    k_hist<<<grid, kBlock, 0, s>>>(d.xyz, d.grids, d.cell_of, d.rank, d.cell_count);
-    scan_excl(d.cell_count, nullptr, c.n_cells - 1, d.scan_part, d.cell_start, nullptr, s);
-    k_scatter<<<grid, kBlock, 0, s>>>(d.xyz, d.grids, d.cell_of, d.rank, d.cell_start, d.sg);
+    k_bbox<<<grid, kBlock, 0, s>>>(d.xyz, d.grids, d.view_of, d.desc);
+    k_grid<<<(c.n_views + 63) / 64, 64, 0, s>>>(d.grids, d.desc, P);
+    k_hist<<<grid, kBlock, 0, s>>>(d.xyz, d.grids, d.cell_of, d.rank, d.cell_count, d.desc);
+    scan_excl(d.cell_count, &d.desc->n_cells_m1, c.n_cells, d.scan_part, d.cell_start, nullptr, s);
+    k_scatter<<<grid, kBlock, 0, s>>>(d.xyz, d.grids, d.cell_of, d.rank, d.cell_start, d.sg,
+                                      d.desc);
 }
 
 void launch_seeds(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
     const uint32_t nb = blocks_for(64ull * c.n_total, 4 * kPersistentBlocks);
     k_seeds<false><<<nb, kBlock, 0, s>>>(d, c, P);
-    scan_excl(d.seed_cnt, nullptr, c.n_total, d.scan_part, d.seed_off, nullptr, s);
+    scan_excl(d.seed_cnt, &d.desc->n_total, c.n_total, d.scan_part, d.seed_off, nullptr, s);
     k_seed_total<<<1, 64, 0, s>>>(d, c);
     k_seeds<true><<<nb, kBlock, 0, s>>>(d, c, P);
 }
@@ -1613,10 +1645,14 @@ void launch_merge(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t 
 
 int max_merge_rounds() { return kMaxRounds; }
 
+void launch_copy_out(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {
+    k_copy_out<<<64, kBlock, 0, s>>>(d, c);
+}
+
 void launch_fit(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
     const uint32_t nb = blocks_for(c.cand_cap, kPersistentBlocks);
     k_collect<<<nb, kBlock, 0, s>>>(d, c);
-    k_view_offsets<<<1, kBlock, 0, s>>>(d, c.n_views);
+    k_view_offsets<<<1, kBlock, 0, s>>>(d);
     // keys of the grouped tracks reuse the owner array (merge is over)
     unsigned long long *gkey = d.owner;
     k_group<<<nb, kBlock, 0, s>>>(d, gkey);

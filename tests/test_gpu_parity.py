@@ -214,3 +214,36 @@ def test_fp64_always_flag(emt, oracle_mod):
     for k, rt in enumerate(ref.tracks):
         for s in range(2):
             assert abs(np.arctan(got["tracks"][k]["slope"][s]) - np.arctan(rt["slope"][s])) < 1e-6
+
+
+def test_graph_replays_match_eager_launches(emt, monkeypatch):
+    """One captured launch sequence serves every batch in its capacity bucket;
+    each replay must equal the eager launches, with unrelated device work and
+    synchronisations in between."""
+    import torch
+    views = [synth.make_c1(i).xyz for i in range(21, 27)]
+    monkeypatch.setenv("EMT_NO_GRAPH", "1")
+    eager = emt.Tracker(device=0)
+    monkeypatch.delenv("EMT_NO_GRAPH")
+    graph = emt.Tracker(device=0)
+    try:
+        junk = torch.zeros(1 << 20, device="cuda:0")
+        for rep in range(3):
+            for x in views:
+                a = eager([x])[0]
+                junk.add_(1.0)
+                torch.cuda.synchronize()
+                b = graph([x])[0]
+                assert a["tracks"].tobytes() == b["tracks"].tobytes(), rep
+                assert np.array_equal(a["grains"], b["grains"])
+                assert a["n_seeds"] == b["n_seeds"] and a["n_candidates"] == b["n_candidates"]
+        # a batch of several views replays its own captured sequence
+        for rep in range(2):
+            ra = eager(views)
+            rb = graph(views)
+            for a, b in zip(ra, rb):
+                assert a["tracks"].tobytes() == b["tracks"].tobytes()
+                assert np.array_equal(a["grains"], b["grains"])
+    finally:
+        eager.close()
+        graph.close()
