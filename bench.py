@@ -8,7 +8,9 @@ um, 300 isotropic tracks (20 % stopping), fog 3 grains per 1000 um^3, about
 
 Prints one JSON line: grains/s (value), mm^2/hour, view latency p50/p99, the
 counting kernel's roofline (HIP events on the library's stream), and the
-CPU oracle timed on one view on this host.
+CPU oracle timed on one view on this host. The same line carries the
+batched form: 64 uneven c3 views per call and 32 dense c5 views per call,
+each through one sequence of launches.
 """
 from __future__ import annotations
 
@@ -62,6 +64,45 @@ def cpu_baseline(view, max_seconds: float = 30.0):
                       f"{dt:.2f} s"}
 
 
+def measure_batch(emt, torch, views, calls: int, warmup: int) -> dict:
+    """Whole-batch calls on device-resident views: throughput, per-call
+    latency, and the counting kernel's share from one call with stage events."""
+    devs = [torch.from_numpy(v.xyz).to("cuda:0").contiguous() for v in views]
+    grains = sum(v.n for v in views)
+    area = sum(v.area_mm2 for v in views)
+    torch.cuda.synchronize()
+    with emt.Tracker(device=0, flags=emt.EMT_F_DEVICE_PTRS) as tr:
+        for _ in range(warmup):
+            tr(devs)
+        lat = []
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            t1 = time.perf_counter()
+            tr(devs)
+            lat.append(time.perf_counter() - t1)
+        wall = time.perf_counter() - t0
+        st0 = tr.stats()
+    with emt.Tracker(device=0, flags=emt.EMT_F_DEVICE_PTRS | emt.EMT_F_STATS) as tr:
+        tr(devs)
+        tr(devs)
+        st = tr.stats()
+    lat_ms = np.array(lat) * 1e3
+    count_s = st["ms"]["count"] * 1e-3
+    achieved = st["n_tests"] * OPS_PER_TEST / count_s / 1e12
+    return {"views_per_call": len(views), "grains_per_call": grains,
+            "grains_per_s": round(grains * calls / wall, 1),
+            "mm2_per_hour": round(area * calls / wall * 3600.0, 2),
+            "ms_per_call": round(wall / calls * 1e3, 3),
+            "call_latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
+                                "p99": round(float(np.percentile(lat_ms, 99)), 3)},
+            "stage_ms": {k: round(v, 3) for k, v in st["ms"].items()},
+            "work": {"seeds": st0["n_seeds"], "tests": st0["n_tests"],
+                     "candidates": st0["n_candidates"], "tracks": st0["n_tracks"],
+                     "merge_rounds": st0["merge_rounds"]},
+            "count_roofline": {"achieved": round(achieved, 3), "unit": "Tops/s",
+                               "frac": round(achieved / (VALU_PEAK_OPS / 1e12), 4)}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +110,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--view-index", type=int, default=0)
+    ap.add_argument("--forms", default="c3,c5",
+                    help="batched workloads to add to the line (comma list of c3, c5; '' for none)")
+    ap.add_argument("--form-calls", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy, the reference "
                          "for scaling FETCH_SIZE/WRITE_SIZE counters")
@@ -149,6 +193,20 @@ def main() -> int:
                      "frac": round(achieved / peak, 4),
                      "traffic": traffic_for_current_kernel(tests)},
     }
+    forms = {}
+    for f in [x for x in args.forms.split(",") if x]:
+        if f == "c3":
+            vs = [synth.make_c3(i) for i in range(64)]
+            forms["batched_c3"] = measure_batch(emt, torch, vs, args.form_calls, 2)
+            forms["batched_c3"]["workload"] = ("c3: 64 views per call, 2k-40k grains each "
+                                               "(log-uniform), 50-500 tracks, fog 1-5/1000 um^3")
+        elif f == "c5":
+            vs = [synth.make_c5(i) for i in range(32)]
+            forms["batched_c5"] = measure_batch(emt, torch, vs, args.form_calls, 1)
+            forms["batched_c5"]["workload"] = ("c5: 32 views per call, 350x350x50 um, 10 stars "
+                                               "of 3-8 prongs, 200 tracks, fog 10/1000 um^3")
+    if forms:
+        out["forms"] = forms
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(view)
     print(json.dumps(out))

@@ -247,3 +247,88 @@ def test_graph_replays_match_eager_launches(emt, monkeypatch):
     finally:
         eager.close()
         graph.close()
+
+
+def _check_track_properties(xyz, got, R=2500, r=50, n_min=8):
+    """Exact checks that hold at any size: every grain of a track lies within
+    r of its seed line, tracks share no grain, each keeps n_min grains, and
+    the grain order follows the seed direction."""
+    g = np.asarray(xyz, np.int64)
+    seen = np.zeros(len(g), bool)
+    for t in got["tracks"]:
+        i, j = int(t["seed"][0]), int(t["seed"][1])
+        d = g[j] - g[i]
+        D = int(d @ d)
+        assert 0 < D < R * R and i < j
+        off, n = int(t["grain_offset"]), int(t["n_grains"])
+        ks = got["grains"][off:off + n].astype(np.int64)
+        assert n >= n_min
+        c = np.cross(g[ks] - g[i], d)
+        assert np.all((c * c).sum(axis=1) <= r * r * D)
+        assert not seen[ks].any()
+        seen[ks] = True
+        tk = (g[ks] - g[i]) @ d
+        assert np.all((np.diff(tk) > 0) | ((np.diff(tk) == 0) & (np.diff(ks) > 0)))
+
+
+def _pair_count(xyz, R=2500):
+    from scipy.spatial import cKDTree
+    pts = np.asarray(xyz, np.float64)
+    pairs = cKDTree(pts).query_pairs(R + 0.5, output_type="ndarray")
+    g = np.asarray(xyz, np.int64)
+    d = g[pairs[:, 1]] - g[pairs[:, 0]]
+    D = (d * d).sum(axis=1)
+    return int(((D > 0) & (D < R * R)).sum())
+
+
+def test_config3_batch_of_64_uneven_views(emt, oracle_mod):
+    import torch
+    views = [synth.make_c3(i) for i in range(64)]
+    _say(f"c3 batch: {sum(v.n for v in views)} grains, sizes {min(v.n for v in views)}..{max(v.n for v in views)}")
+    with emt.Tracker(device=0, flags=emt.EMT_F_DEVICE_PTRS) as t:
+        devs = [torch.from_numpy(v.xyz).to("cuda:0") for v in views]
+        batch = t(devs)
+        alone = [t([x])[0] for x in devs]
+    for a, b in zip(alone, batch):
+        assert a["tracks"].tobytes() == b["tracks"].tobytes()
+        assert np.array_equal(a["grains"], b["grains"])
+        assert a["n_seeds"] == b["n_seeds"] and a["n_candidates"] == b["n_candidates"]
+    small = sorted(range(64), key=lambda k: views[k].n)[:4]
+    for k in small:
+        _say(f"c3 view {k}: {views[k].n} grains vs oracle")
+        assert_view_parity(views[k].xyz, batch[k], oracle_mod.track_view(views[k].xyz))
+
+
+def test_config5_group_properties_and_alone_equals_batch(emt):
+    views = [synth.make_c5(i) for i in range(4)]
+    with emt.Tracker(device=0) as t:
+        batch = t([v.xyz for v in views])
+        for v, b in zip(views, batch):
+            a = t([v.xyz])[0]
+            assert a["tracks"].tobytes() == b["tracks"].tobytes()
+            assert np.array_equal(a["grains"], b["grains"])
+            assert b["n_seeds"] == _pair_count(v.xyz)
+            _check_track_properties(v.xyz, b)
+            assert len(b["tracks"]) > 1000
+
+
+def test_config5_dense_crop_matches_oracle(emt, oracle_mod):
+    v = synth.make_c5(5)
+    x = v.xyz
+    lo = np.array([10000, 10000, -1000])
+    keep = np.all((x >= lo) & (x < lo + np.array([12000, 12000, 7000])), axis=1)
+    crop = x[keep]
+    _say(f"c5 crop: {len(crop)} grains")
+    with emt.Tracker(device=0) as t:
+        got = t([crop])[0]
+    assert_view_parity(crop, got, oracle_mod.track_view(crop))
+
+
+def test_config4_mixed_sizes_match_oracle(emt, oracle_mod):
+    with emt.Tracker(device=0) as t:
+        for i in range(6):
+            v = synth.make_c4(i)
+            if v.n > 15000:
+                continue
+            _say(f"c4 view {i}: {v.n} grains")
+            assert_view_parity(v.xyz, t([v.xyz])[0], oracle_mod.track_view(v.xyz))
