@@ -1084,11 +1084,11 @@ __global__ void __launch_bounds__(kBlock) k_cand_n(DevPtrs d, Caps c) {
 //            is accepted with that set if it still has n_min grains.
 // Accepted candidates of one round own disjoint grains, so their updates do
 // not interact, and a concurrent update can only hide grains taken by a
-// higher-priority accepted candidate. One wave handles one candidate, lanes
-// its member entries; decided candidates cost one status read.
+// higher-priority accepted candidate. The grid-wide rounds fuse prune and
+// reserve into one pass; the tail kernel keeps the three phases.
 
 constexpr int kMaxRounds = 256;
-constexpr int kWideRounds = 6;  // rounds run grid-wide before the tail kernel
+constexpr int kWideRounds = 16;  // grid-wide rounds (distinct key tags) before the tail
 
 __global__ void __launch_bounds__(kBlock) k_merge_init(DevPtrs d, Caps c) {
     const Counters *cn = d.cnt;
@@ -1109,163 +1109,218 @@ __global__ void __launch_bounds__(kBlock) k_merge_init(DevPtrs d, Caps c) {
     for (uint32_t r = grid_tid(); r < kMaxRounds; r += grid_threads()) d.undecided[r] = 0;
     if (grid_tid() == 0) {
         d.cnt->n_act[0] = nc;  // candidates taking part in the merge
-        d.cnt->n_act[1] = 0;   // candidates left for the tail kernel
+        d.cnt->n_act[1] = 0;
         d.cnt->err |= overflow ? 1u : 0u;
     }
 }
 
+// Grid-wide rounds. Eight lanes take one candidate and stride over its
+// member entries; round r walks the list of candidates left undecided by
+// round r-1 (all candidates for r = 0) and appends the ones it leaves
+// undecided to the next list, whose length it counts in undecided[r]. A
+// reservation carries its round in the top four bits of the key, counted
+// down, so the keys of a newer round lie below every older value and no
+// clearing pass is needed between rounds (keys use 60 bits: n, i and j are
+// below 2^20 each).
+constexpr int kMergeGroup = 8;
+static_assert(kWideRounds <= 16, "round tags take four bits");
+
+__device__ __forceinline__ uint32_t group_sum8(uint32_t v) {
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 1);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t *merge_list(const DevPtrs &d, int round) {
+    return (round & 1) ? d.act2 : d.act;
+}
+
+// Candidates left undecided are staged in LDS and appended to the next list
+// with one global atomic per flush: a single counter hit once per wave
+// serialises at the L2.
+constexpr uint32_t kListBuf = 2048;
+constexpr uint32_t kGroupsPerBlock = kBlock / kMergeGroup;
+
+__device__ __forceinline__ void flush_list(uint32_t *s_buf, uint32_t *s_cnt, uint32_t *s_base,
+                                           uint32_t *counter, uint32_t *next) {
+    __syncthreads();
+    const uint32_t m = *s_cnt;
+    if (threadIdx.x == 0 && m) *s_base = atomicAdd(counter, m);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) next[*s_base + i] = s_buf[i];
+    __syncthreads();
+    if (threadIdx.x == 0) *s_cnt = 0;
+    __syncthreads();
+}
+
 template <int kPhase>
-__global__ void __launch_bounds__(kBlock) k_round(DevPtrs d, Params P, int round, int append) {
-    const uint32_t n = d.cnt->n_act[0];
-    if (round > 0 && d.undecided[round - 1] == 0) return;
-    const int lane = lane_id();
-    const uint32_t gw = grid_tid() >> 6, nw = grid_threads() >> 6;
-    uint32_t still = 0;
-    for (uint32_t ci = gw; ci < n; ci += nw) {
-        if (d.status[ci] != kUndecided) continue;
-        const unsigned long long key = d.key[ci];
-        const uint32_t e0 = d.mem_off[ci], ne = d.cand[ci].n;
-        if (kPhase == 0) {  // prune
-            uint32_t unused = 0;
-            for (uint32_t e = lane; e < ne; e += 64) {
-                const uint32_t k = d.members[e0 + e];
-                if (!d.used[k]) {
-                    ++unused;
-                    d.owner[k] = ~0ull;
-                }
-            }
-            unused = wave_sum(unused);
-            if (unused < (uint32_t)P.n_min && lane == 0) d.status[ci] = kRejected;
-        } else if (kPhase == 1) {  // reserve
-            for (uint32_t e = lane; e < ne; e += 64) {
-                const uint32_t k = d.members[e0 + e];
-                if (!d.used[k]) atomicMin(&d.owner[k], key);
-            }
-        } else {  // decide
-            uint32_t unused = 0;
-            bool owns = true;
-            for (uint32_t e = lane; e < ne; e += 64) {
-                const uint32_t k = d.members[e0 + e];
-                if (!d.used[k]) {
-                    ++unused;
-                    owns = owns && d.owner[k] == key;
-                }
-            }
-            unused = wave_sum(unused);
-            owns = __ballot(!owns) == 0;
-            if (unused < (uint32_t)P.n_min) {
-                if (lane == 0) d.status[ci] = kRejected;
-            } else if (owns) {
-                for (uint32_t e = lane; e < ne; e += 64) {
-                    const uint32_t k = d.members[e0 + e];
-                    if (!d.used[k]) {
-                        d.used[k] = 1;
-                        d.taken[e0 + e] = 1;
+__global__ void __launch_bounds__(kBlock) k_round(DevPtrs d, Params P, int round) {
+    __shared__ uint32_t s_buf[kPhase == 1 ? kListBuf : 1];
+    __shared__ uint32_t s_cnt, s_base;
+    const uint32_t n = round == 0 ? d.cnt->n_act[0] : d.undecided[round - 1];
+    if (n == 0) return;
+    const uint32_t *list = merge_list(d, round);
+    uint32_t *next = merge_list(d, round + 1);
+    const unsigned long long tag = (unsigned long long)(kWideRounds - 1 - round) << 60;
+    const int sub = threadIdx.x & (kMergeGroup - 1);
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    // block-uniform loop: the list flush below synchronises the workgroup
+    for (uint32_t base = blockIdx.x * kGroupsPerBlock; base < n;
+         base += gridDim.x * kGroupsPerBlock) {
+        const uint32_t slot = base + threadIdx.x / kMergeGroup;
+        uint32_t ci = 0;
+        bool live = slot < n;
+        if (live) {
+            ci = round == 0 ? slot : list[slot];
+            live = round == 0 || d.status[ci] == kUndecided;
+        }
+        bool still = false;
+        if (live) {
+            const unsigned long long key = d.key[ci] | tag;
+            const uint32_t e0 = d.mem_off[ci], e1 = e0 + d.cand[ci].n;
+            if (kPhase == 0) {  // prune, then reserve
+                uint32_t unused = 0;
+                for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup)
+                    unused += d.used[d.members[e]] ? 0u : 1u;
+                unused = group_sum8(unused);
+                if (unused < (uint32_t)P.n_min) {
+                    if (sub == 0) d.status[ci] = kRejected;
+                } else {
+                    for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
+                        const uint32_t k = d.members[e];
+                        if (!d.used[k]) atomicMin(&d.owner[k], key);
                     }
                 }
-                if (lane == 0) {
-                    d.mcount[ci] = unused;
-                    d.status[ci] = kAccepted;
+            } else {  // decide
+                uint32_t unused = 0, lost = 0;
+                for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
+                    const uint32_t k = d.members[e];
+                    if (!d.used[k]) {
+                        ++unused;
+                        lost |= d.owner[k] != key ? 1u : 0u;
+                    }
                 }
-            } else {
-                ++still;
-                if (append && lane == 0) {
-                    // the tail kernel continues from this list
-                    const uint32_t slot = atomicAdd(&d.cnt->n_act[1], 1u);
-                    d.act[slot] = ci;
+                unused = group_sum8(unused);
+                lost = group_sum8(lost);
+                if (unused < (uint32_t)P.n_min) {
+                    if (sub == 0) d.status[ci] = kRejected;
+                } else if (lost == 0) {
+                    for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
+                        const uint32_t k = d.members[e];
+                        if (!d.used[k]) {
+                            d.used[k] = 1;
+                            d.taken[e] = 1;
+                        }
+                    }
+                    if (sub == 0) {
+                        d.mcount[ci] = unused;
+                        d.status[ci] = kAccepted;
+                    }
+                } else {
+                    still = sub == 0;
                 }
             }
         }
+        if (kPhase == 1) {
+            if (still) s_buf[atomicAdd(&s_cnt, 1u)] = ci;
+            __syncthreads();
+            const uint32_t held = s_cnt;
+            __syncthreads();  // all have read it before the next iteration adds
+            if (held + kGroupsPerBlock > kListBuf)
+                flush_list(s_buf, &s_cnt, &s_base, &d.undecided[round], next);
+        }
     }
-    // only "any left" matters: every writer stores the same value
-    if (kPhase == 2 && lane == 0 && still) d.undecided[round] = 1u;
+    if (kPhase == 1) flush_list(s_buf, &s_cnt, &s_base, &d.undecided[round], next);
 }
 
 // The remaining rounds in one workgroup, looping until no candidate is
 // undecided (each round decides at least the highest-priority one, so it
-// ends within as many rounds as there are candidates). Waves take
-// candidates of the list; __syncthreads separates the phases.
+// ends within as many rounds as there are candidates). Groups of eight lanes
+// take candidates of the list; __syncthreads separates the phases, and the
+// prune phase clears the reservations of the candidates' unused grains.
 constexpr int kTailBlock = 1024;
 
 __global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, int last_round) {
     __shared__ uint32_t s_n[2];
-    const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
-    constexpr int kTailWaves = kTailBlock / 64;
+    const int sub = threadIdx.x & (kMergeGroup - 1);
+    const uint32_t group = threadIdx.x / kMergeGroup;
+    constexpr uint32_t kTailGroups = kTailBlock / kMergeGroup;
     if (threadIdx.x == 0) {
-        s_n[0] = d.undecided[last_round] ? d.cnt->n_act[1] : 0u;
+        s_n[0] = d.undecided[last_round];
         s_n[1] = 0;
     }
     __syncthreads();
-    uint32_t *list[2] = {d.act, d.act2};
+    uint32_t *list[2] = {merge_list(d, last_round + 1), merge_list(d, last_round + 2)};
     int cur = 0;
     uint32_t rounds = 0;
     const uint32_t limit = s_n[0] + 2;
     while (s_n[cur] > 0 && rounds < limit) {
         const uint32_t n = s_n[cur];
-        // prune
-        for (uint32_t i = wave; i < n; i += kTailWaves) {
+        // prune (groups are whole 8-lane slices of one wave, so the group
+        // sums only read lanes that took the same branch)
+        for (uint32_t i = group; i < n; i += kTailGroups) {
             const uint32_t ci = list[cur][i];
             if (d.status[ci] != kUndecided) continue;
-            const uint32_t e0 = d.mem_off[ci], ne = d.cand[ci].n;
+            const uint32_t e0 = d.mem_off[ci], e1 = e0 + d.cand[ci].n;
             uint32_t unused = 0;
-            for (uint32_t e = lane; e < ne; e += 64) {
-                const uint32_t k = d.members[e0 + e];
+            for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
+                const uint32_t k = d.members[e];
                 if (!d.used[k]) {
                     ++unused;
                     d.owner[k] = ~0ull;
                 }
             }
-            unused = wave_sum(unused);
-            if (unused < (uint32_t)P.n_min && lane == 0) d.status[ci] = kRejected;
+            unused = group_sum8(unused);
+            if (unused < (uint32_t)P.n_min && sub == 0) d.status[ci] = kRejected;
         }
         __threadfence_block();
         __syncthreads();
         // reserve
-        for (uint32_t i = wave; i < n; i += kTailWaves) {
+        for (uint32_t i = group; i < n; i += kTailGroups) {
             const uint32_t ci = list[cur][i];
             if (d.status[ci] != kUndecided) continue;
             const unsigned long long key = d.key[ci];
-            const uint32_t e0 = d.mem_off[ci], ne = d.cand[ci].n;
-            for (uint32_t e = lane; e < ne; e += 64) {
-                const uint32_t k = d.members[e0 + e];
+            const uint32_t e0 = d.mem_off[ci], e1 = e0 + d.cand[ci].n;
+            for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
+                const uint32_t k = d.members[e];
                 if (!d.used[k]) atomicMin(&d.owner[k], key);
             }
         }
         __threadfence_block();
         __syncthreads();
         // decide
-        for (uint32_t i = wave; i < n; i += kTailWaves) {
+        for (uint32_t i = group; i < n; i += kTailGroups) {
             const uint32_t ci = list[cur][i];
             if (d.status[ci] != kUndecided) continue;
             const unsigned long long key = d.key[ci];
-            const uint32_t e0 = d.mem_off[ci], ne = d.cand[ci].n;
-            uint32_t unused = 0;
-            bool owns = true;
-            for (uint32_t e = lane; e < ne; e += 64) {
-                const uint32_t k = d.members[e0 + e];
+            const uint32_t e0 = d.mem_off[ci], e1 = e0 + d.cand[ci].n;
+            uint32_t unused = 0, lost = 0;
+            for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
+                const uint32_t k = d.members[e];
                 if (!d.used[k]) {
                     ++unused;
-                    owns = owns && d.owner[k] == key;
+                    lost |= d.owner[k] != key ? 1u : 0u;
                 }
             }
-            unused = wave_sum(unused);
-            owns = __ballot(!owns) == 0;
+            unused = group_sum8(unused);
+            lost = group_sum8(lost);
             if (unused < (uint32_t)P.n_min) {
-                if (lane == 0) d.status[ci] = kRejected;
-            } else if (owns) {
-                for (uint32_t e = lane; e < ne; e += 64) {
-                    const uint32_t k = d.members[e0 + e];
+                if (sub == 0) d.status[ci] = kRejected;
+            } else if (lost == 0) {
+                for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
+                    const uint32_t k = d.members[e];
                     if (!d.used[k]) {
                         d.used[k] = 1;
-                        d.taken[e0 + e] = 1;
+                        d.taken[e] = 1;
                     }
                 }
-                if (lane == 0) {
+                if (sub == 0) {
                     d.mcount[ci] = unused;
                     d.status[ci] = kAccepted;
                 }
-            } else if (lane == 0) {
+            } else if (sub == 0) {
                 const uint32_t slot = atomicAdd(&s_n[cur ^ 1], 1u);
                 list[cur ^ 1][slot] = ci;
             }
@@ -1278,7 +1333,10 @@ __global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        d.cnt->rounds = (uint32_t)last_round + 1u + rounds;
+        // grid-wide rounds that ran: round r runs while round r-1 left some
+        uint32_t wide = d.cnt->n_act[0] ? 1u : 0u;
+        while (wide >= 1 && wide <= (uint32_t)last_round && d.undecided[wide - 1]) ++wide;
+        d.cnt->rounds = wide + rounds;
         if (s_n[cur] > 0) d.cnt->err |= 4u;
     }
 }
@@ -1634,11 +1692,13 @@ void launch_merge_init(const DevPtrs &d, const Caps &c, const Params &, hipStrea
 }
 
 void launch_merge(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
-    const uint32_t nb = blocks_for(64ull * c.cand_cap, 4 * kPersistentBlocks);
+    // Later rounds see a fraction of the candidates: their grids shrink by
+    // half per round down to a floor (the loops stride, so any grid is correct).
+    uint32_t nb = blocks_for((unsigned long long)kMergeGroup * c.cand_cap, 2 * kPersistentBlocks);
     for (int round = 0; round < kWideRounds; ++round) {
-        k_round<0><<<nb, kBlock, 0, s>>>(d, P, round, 0);
-        k_round<1><<<nb, kBlock, 0, s>>>(d, P, round, 0);
-        k_round<2><<<nb, kBlock, 0, s>>>(d, P, round, round == kWideRounds - 1);
+        k_round<0><<<nb, kBlock, 0, s>>>(d, P, round);
+        k_round<1><<<nb, kBlock, 0, s>>>(d, P, round);
+        if (round >= 1 && nb > 1024) nb = nb / 2 > 1024 ? nb / 2 : 1024;
     }
     k_merge_tail<<<1, kTailBlock, 0, s>>>(d, P, kWideRounds - 1);
 }
