@@ -103,6 +103,85 @@ def measure_batch(emt, torch, views, calls: int, warmup: int) -> dict:
                                "frac": round(achieved / (VALU_PEAK_OPS / 1e12), 4)}}
 
 
+def measure_served(emt, views, n_req: int, warmup: int, batch: int = 16,
+                   fracs=(0.5, 0.9), seed: int = 0x5E4FE) -> dict:
+    """The served form on a pool of c4 views (host arrays, as a microscope
+    hands them over). First the batched capacity mu_b (views/s through
+    emt_track_views, batch views per call) and the plain one-view-per-call
+    rate; then a Poisson stream at each fraction of mu_b through the server,
+    with latency = completion - submission per view."""
+    import threading
+    xyzs = [v.xyz for v in views]
+    area = np.array([v.area_mm2 for v in views])
+    ngr = np.array([v.n for v in views])
+    out = {"pool_views": len(views), "pool_mean_grains": round(float(ngr.mean()), 1)}
+    with emt.Tracker(device=0) as tr:
+        for k in range(0, len(xyzs), batch):
+            tr(xyzs[k:k + batch])
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            for k in range(0, len(xyzs), batch):
+                tr(xyzs[k:k + batch])
+        mu_b = reps * len(xyzs) / (time.perf_counter() - t0)
+        lat = []
+        t0 = time.perf_counter()
+        for x in xyzs:
+            t1 = time.perf_counter()
+            tr([x])
+            lat.append(time.perf_counter() - t1)
+        plain_rate = len(xyzs) / (time.perf_counter() - t0)
+    lat = np.array(lat) * 1e3
+    out["batched_capacity_views_per_s"] = round(mu_b, 1)
+    out["plain"] = {"views_per_s": round(plain_rate, 1),
+                    "grains_per_s": round(plain_rate * float(ngr.mean()), 1),
+                    "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                                   "p99": round(float(np.percentile(lat, 99)), 3)}}
+    rng = np.random.default_rng(seed)
+    runs = []
+    for frac in fracs:
+        lam = frac * mu_b
+        total = n_req + warmup
+        pick = rng.integers(0, len(xyzs), total)
+        gaps = rng.exponential(1.0 / lam, total)
+        with emt.Server(n_pipes=2, max_batch_views=64, device=0) as srv:
+            def feed():
+                t_next = time.perf_counter()
+                for k in range(total):
+                    t_next += gaps[k]
+                    dt = t_next - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                    srv.submit(xyzs[pick[k]], view_id=k)
+            th = threading.Thread(target=feed)
+            th.start()
+            res = {}
+            while len(res) < total:
+                for r in srv.poll(wait_ms=50):
+                    res[r["view_id"]] = (r["status"], r["t_submit_ms"], r["t_done_ms"],
+                                         r["batch_views"])
+            th.join()
+            st = srv.stats()
+        ks = np.arange(warmup, total)
+        bad = sum(1 for k in ks if res[k][0] != 0)
+        sub = np.array([res[k][1] for k in ks])
+        done = np.array([res[k][2] for k in ks])
+        lat = done - sub
+        win_s = (done.max() - sub.min()) * 1e-3
+        runs.append({"lambda_frac_of_mu_b": frac, "lambda_views_per_s": round(lam, 1),
+                     "microscopes_at_5hz": round(lam / 5.0, 1),
+                     "requests": int(n_req), "warmup": int(warmup), "errors": int(bad),
+                     "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                                    "p99": round(float(np.percentile(lat, 99)), 3)},
+                     "grains_per_s": round(float(ngr[pick[ks]].sum()) / win_s, 1),
+                     "mm2_per_hour": round(float(area[pick[ks]].sum()) / win_s * 3600.0, 2),
+                     "mean_batch_views": round(float(np.mean([res[k][3] for k in ks])), 2),
+                     "device_busy_frac": round(st["busy_ms"] / st["elapsed_ms"], 3),
+                     "two_batches_on_device_frac": round(st["overlap_ms"] / st["elapsed_ms"], 3)})
+    out["served"] = runs
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,8 +189,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--view-index", type=int, default=0)
-    ap.add_argument("--forms", default="c3,c5",
-                    help="batched workloads to add to the line (comma list of c3, c5; '' for none)")
+    ap.add_argument("--forms", default="c3,c5,c4",
+                    help="other forms to add to the line (comma list of c3, c5 batched and "
+                         "c4 served; '' for none)")
+    ap.add_argument("--served-requests", type=int, default=5000)
+    ap.add_argument("--served-warmup", type=int, default=500)
     ap.add_argument("--form-calls", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy, the reference "
@@ -205,6 +287,12 @@ def main() -> int:
             forms["batched_c5"] = measure_batch(emt, torch, vs, args.form_calls, 1)
             forms["batched_c5"]["workload"] = ("c5: 32 views per call, 350x350x50 um, 10 stars "
                                                "of 3-8 prongs, 200 tracks, fog 10/1000 um^3")
+        elif f == "c4":
+            vs = [synth.make_c4(i) for i in range(96)]
+            forms["served_c4"] = measure_served(emt, vs, args.served_requests, args.served_warmup)
+            forms["served_c4"]["workload"] = (
+                "c4: Poisson stream drawn from 96 views of 100^2, 200^2 or 350^2 x 50 um, "
+                "fog 1-10/1000 um^3, 2449 tracks/mm^2; two pipelines, up to 64 views a batch")
     if forms:
         out["forms"] = forms
     if not args.no_cpu_baseline:

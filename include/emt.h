@@ -180,6 +180,79 @@ void emt_destroy(emt_ctx *ctx);
 /* Static text for a return code. */
 const char *emt_strerror(int code);
 
+/*
+ * Serving (paper, Sec. 3: the microscope delivers one view after another at
+ * up to 5 Hz, and views are processed in parallel threads sharing the GPUs).
+ * A server tracks views as they arrive. A worker thread runs n_pipes
+ * pipelines, each a context with its own stream and device buffers; when a
+ * pipeline is free it takes the views waiting, in arrival order, as many as
+ * fit its share (1/n_pipes) of the HBM budget and at most max_batch_views,
+ * as one batch. With n_pipes >= 2 a new batch starts while another is still
+ * on the device. A view's tracks are identical to tracking it alone.
+ *
+ * cfg is as for emt_create; EMT_F_DEVICE_PTRS is rejected (EMT_EINVAL):
+ * submissions are host arrays. Calls on one server may come from several
+ * host threads.
+ */
+typedef struct emt_server emt_server;
+
+/* One finished view. tracks/grains are as in emt_view_out, owned by the
+ * server and valid until the next emt_server_poll on it or
+ * emt_server_destroy. status: EMT_OK, or the error of its batch (EMT_ENOMEM
+ * if the view alone exceeds a pipeline's share of the budget); on error no
+ * tracks are returned. Times are milliseconds since emt_server_create:
+ * submission, admission into a batch, and completion as seen by the
+ * worker. */
+typedef struct {
+    uint64_t ticket;
+    uint64_t view_id;
+    int32_t status;
+    uint32_t n_tracks;
+    uint32_t n_track_grains;
+    uint32_t batch_views; /* views in the batch this one ran in */
+    const emt_track *tracks;
+    const uint32_t *grains;
+    emt_view_stats stats;
+    double t_submit_ms;
+    double t_admit_ms;
+    double t_done_ms;
+} emt_served;
+
+typedef struct {
+    uint64_t submitted;
+    uint64_t completed;
+    uint64_t batches;
+    uint32_t max_batch_views_seen;
+    uint32_t n_pipes;
+    double busy_ms;    /* time with at least one batch on the device  */
+    double overlap_ms; /* time with two or more batches on the device */
+    double elapsed_ms; /* since emt_server_create                     */
+} emt_server_stats;
+
+/* Create a server: 1 <= n_pipes <= 8, max_batch_views >= 1. */
+int emt_server_create(const emt_config *cfg, uint32_t n_pipes,
+                      uint32_t max_batch_views, emt_server **out);
+
+/* Queue one view; its grains are copied before the call returns. *ticket
+ * (may be NULL) receives a number that increases with every submission.
+ * Returns EMT_EINVAL/EMT_ERANGE as emt_validate would, or the server's
+ * sticky EMT_EDEVICE. */
+int emt_server_submit(emt_server *srv, const emt_view_in *view,
+                      uint64_t *ticket);
+
+/* Collect up to max_out finished views, in completion order. wait_ms: 0
+ * returns at once, > 0 waits up to that long for one, < 0 waits until one
+ * is there. Returns EMT_OK or the sticky EMT_EDEVICE after a device error. */
+int emt_server_poll(emt_server *srv, emt_served *out, uint32_t max_out,
+                    uint32_t *n_out, int32_t wait_ms);
+
+/* Counters since creation. */
+int emt_server_get_stats(emt_server *srv, emt_server_stats *stats);
+
+/* Stop admitting, wait for the batches on the device, release everything.
+ * Views still waiting are dropped. NULL is ignored. */
+void emt_server_destroy(emt_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "emt_dev.h"
+#include "emt_host.h"
 
 using namespace emt;
 
@@ -44,6 +45,7 @@ struct emt_ctx {
     bool own_stream = false;
     bool poisoned = false;
     hipEvent_t ev[EMT_N_STAGES + 1] = {};
+    hipEvent_t done = nullptr;  // end of the last enqueued attempt
     size_t budget = 0;
     size_t held = 0;
 
@@ -67,6 +69,14 @@ struct emt_ctx {
     size_t cap_vs = 0, cap_vc = 0, cap_vn = 0, cap_vo = 0, cap_ve = 0;
 
     emt_call_stats last{};
+
+    // the batch between begin and finish
+    struct Pending {
+        const emt_view_in *views = nullptr;
+        uint32_t n_views = 0;
+        Caps caps{};
+        bool active = false;
+    } pend;
 
     // captured launch sequences, keyed by capacities and buffer generation
     struct GraphEntry {
@@ -210,6 +220,36 @@ int mapped(emt_ctx *ctx, T *&host, T *&dev, size_t &cap, size_t n) {
     return EMT_OK;
 }
 
+// Device bytes of each arena for a capacity (ensure carves them in this
+// layout).
+size_t grain_bytes(size_t n) {
+    return bytes_of<int32_t>(3 * n) + 4 * bytes_of<uint32_t>(n) + bytes_of<uint32_t>(n + 1) +
+           bytes_of<int4>(n) + bytes_of<uint8_t>(n) + bytes_of<unsigned long long>(n);
+}
+size_t seed_bytes(size_t n) {
+    return bytes_of<uint2>(n) + bytes_of<uint32_t>(n) + bytes_of<uint32_t>(n + 1);
+}
+size_t cand_bytes(size_t n) {
+    return bytes_of<Cand>(n) + bytes_of<unsigned long long>(n) + 4 * bytes_of<uint32_t>(n + 1) +
+           6 * bytes_of<uint32_t>(n) + bytes_of<uint8_t>(n) + bytes_of<emt_track>(n);
+}
+size_t mem_bytes(size_t n) {
+    return 3 * bytes_of<uint32_t>(n) + bytes_of<uint8_t>(n) + bytes_of<long long>(n);
+}
+size_t cell_bytes(size_t n) {
+    return 2 * bytes_of<uint32_t>(n) + bytes_of<uint32_t>(scan_scratch_words((uint32_t)n));
+}
+size_t view_bytes(size_t n) {
+    return bytes_of<ViewGrid>(n) + bytes_of<unsigned long long>(n) + 4 * bytes_of<uint32_t>(n + 1) +
+           bytes_of<Counters>(1) + bytes_of<uint32_t>((size_t)max_merge_rounds()) +
+           bytes_of<BatchDesc>(1);
+}
+// the scan scratch serves every scan: cells, anchors, seeds, candidates
+uint32_t scan_words(const Caps &c) {
+    return std::max<uint32_t>(std::max<uint32_t>(c.n_cells, c.cand_cap),
+                              std::max<uint32_t>((uint32_t)c.seed_cap, c.n_total)) + 1;
+}
+
 // Make every buffer hold the capacities in c, carve the pointer table, and
 // raise c to what the buffers hold.
 int ensure(emt_ctx *ctx, Caps &c) {
@@ -217,9 +257,7 @@ int ensure(emt_ctx *ctx, Caps &c) {
     DevPtrs &d = ctx->d;
     if (c.n_total > ctx->cap_n || !ctx->grain_buf.p) {
         const size_t n = std::max<uint32_t>(c.n_total, 1024);
-        const size_t b = bytes_of<int32_t>(3 * n) + 4 * bytes_of<uint32_t>(n) +
-                         bytes_of<uint32_t>(n + 1) + bytes_of<int4>(n) + bytes_of<uint8_t>(n) +
-                         bytes_of<unsigned long long>(n);
+        const size_t b = grain_bytes(n);
         if ((rc = arena(ctx, ctx->grain_buf, b))) return rc;
         char *p = (char *)ctx->grain_buf.p;
         d.xyz = carve<int32_t>(p, 3 * n);
@@ -235,7 +273,7 @@ int ensure(emt_ctx *ctx, Caps &c) {
     }
     if (c.seed_cap > ctx->cap_seeds || !ctx->seed_buf.p) {
         const size_t n = c.seed_cap;
-        const size_t b = bytes_of<uint2>(n) + bytes_of<uint32_t>(n) + bytes_of<uint32_t>(n + 1);
+        const size_t b = seed_bytes(n);
         if ((rc = arena(ctx, ctx->seed_buf, b))) return rc;
         char *p = (char *)ctx->seed_buf.p;
         d.seeds = carve<uint2>(p, n);
@@ -245,9 +283,7 @@ int ensure(emt_ctx *ctx, Caps &c) {
     }
     if (c.cand_cap > ctx->cap_cand || !ctx->cand_buf.p) {
         const size_t n = c.cand_cap;
-        const size_t b = bytes_of<Cand>(n) + bytes_of<unsigned long long>(n) +
-                         4 * bytes_of<uint32_t>(n + 1) + 6 * bytes_of<uint32_t>(n) +
-                         bytes_of<uint8_t>(n) + bytes_of<emt_track>(n);
+        const size_t b = cand_bytes(n);
         if ((rc = arena(ctx, ctx->cand_buf, b))) return rc;
         char *p = (char *)ctx->cand_buf.p;
         d.cand = carve<Cand>(p, n);
@@ -268,7 +304,7 @@ int ensure(emt_ctx *ctx, Caps &c) {
     }
     if (c.mem_cap > ctx->cap_mem || !ctx->mem_buf.p) {
         const size_t n = c.mem_cap;
-        const size_t b = 3 * bytes_of<uint32_t>(n) + bytes_of<uint8_t>(n) + bytes_of<long long>(n);
+        const size_t b = mem_bytes(n);
         if ((rc = arena(ctx, ctx->mem_buf, b))) return rc;
         char *p = (char *)ctx->mem_buf.p;
         d.members = carve<uint32_t>(p, n);
@@ -281,13 +317,10 @@ int ensure(emt_ctx *ctx, Caps &c) {
     c.seed_cap = std::max<unsigned long long>(c.seed_cap, ctx->cap_seeds);
     c.cand_cap = std::max(c.cand_cap, ctx->cap_cand);
     c.mem_cap = std::max(c.mem_cap, ctx->cap_mem);
-    // the scan scratch serves every scan: cells, anchors, seeds, candidates
-    const uint32_t scan_cap =
-        std::max<uint32_t>(std::max<uint32_t>(c.n_cells, c.cand_cap),
-                           std::max<uint32_t>((uint32_t)c.seed_cap, c.n_total)) + 1;
+    const uint32_t scan_cap = scan_words(c);
     if (scan_cap > ctx->cap_cells || !ctx->cell_buf.p) {
         const size_t n = std::max<uint32_t>(scan_cap, 1u << 16);
-        const size_t b = 2 * bytes_of<uint32_t>(n) + bytes_of<uint32_t>(scan_scratch_words((uint32_t)n));
+        const size_t b = cell_bytes(n);
         if ((rc = arena(ctx, ctx->cell_buf, b))) return rc;
         char *p = (char *)ctx->cell_buf.p;
         d.cell_count = carve<uint32_t>(p, n);
@@ -297,9 +330,7 @@ int ensure(emt_ctx *ctx, Caps &c) {
     }
     if (c.n_views > ctx->cap_views || !ctx->view_buf.p) {
         const size_t n = std::max<uint32_t>(c.n_views, 64);
-        const size_t b = bytes_of<ViewGrid>(n) + bytes_of<unsigned long long>(n) +
-                         4 * bytes_of<uint32_t>(n + 1) + bytes_of<Counters>(1) +
-                         bytes_of<uint32_t>((size_t)max_merge_rounds()) + bytes_of<BatchDesc>(1);
+        const size_t b = view_bytes(n);
         if ((rc = arena(ctx, ctx->view_buf, b))) return rc;
         char *p = (char *)ctx->view_buf.p;
         d.grids = carve<ViewGrid>(p, n);
@@ -454,13 +485,11 @@ int launch_sequence(emt_ctx *ctx, const Caps &c) {
     return EMT_OK;
 }
 
-// One attempt at the whole batch. Returns EMT_OK, EMT_EOVERFLOW (caps too
-// small: ctx->h.cnt holds the needs) or an error.
-int run_once(emt_ctx *ctx, const emt_view_in *views, uint32_t nv, const Caps &c,
-             bool *overflow) {
+// Enqueue one attempt at the whole batch on the context's stream: staging
+// copies, then the kernel sequence. Nothing waits.
+int run_launch(emt_ctx *ctx, const emt_view_in *views, uint32_t nv, const Caps &c) {
     DevPtrs &d = ctx->d;
     hipStream_t s = ctx->stream;
-    *overflow = false;
     record(ctx, 0);
     // stage the grains into the packed buffer
     const bool dev = (ctx->cfg.flags & EMT_F_DEVICE_PTRS) != 0;
@@ -483,8 +512,15 @@ int run_once(emt_ctx *ctx, const emt_view_in *views, uint32_t nv, const Caps &c,
         ctx->poisoned = true;
         return rc;
     }
-    if (!(ctx->cfg.flags & EMT_F_STATS)) record(ctx, 8);
-    HIP_OK(hipStreamSynchronize(s));
+    HIP_OK(hipEventRecord(ctx->done, s));
+    return EMT_OK;
+}
+
+// Wait for the attempt enqueued by run_launch. Returns EMT_OK,
+// EMT_EOVERFLOW (caps too small: ctx->h.cnt holds the needs) or an error.
+int run_check(emt_ctx *ctx, const Caps &c, bool *overflow) {
+    *overflow = false;
+    HIP_OK(hipEventSynchronize(ctx->done));
     const Counters &h = *ctx->h.cnt;
     if (h.n_seeds > c.seed_cap || h.n_cand > c.cand_cap || h.n_members > c.mem_cap) {
         *overflow = true;
@@ -497,11 +533,50 @@ int run_once(emt_ctx *ctx, const emt_view_in *views, uint32_t nv, const Caps &c,
     return EMT_OK;
 }
 
+// Per-view grid records for one attempt (the device overwrites them).
+void fill_grids(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views) {
+    uint32_t go = 0, co = 0;
+    for (uint32_t v = 0; v < n_views; ++v) {
+        ViewGrid &G = ctx->h_grids[v];
+        G = ViewGrid{};
+        for (int m = 0; m < 3; ++m) {
+            G.lo[m] = INT32_MAX;
+            G.hi[m] = INT32_MIN;
+        }
+        G.grain_off = go;
+        G.n = views[v].n_grains;
+        G.cell_off = co;
+        G.cell_cap = 4u * views[v].n_grains + 4096u;
+        go += G.n;
+        co += G.cell_cap + 1;
+    }
+}
+
 // Capacity bucket: the next power of two, at least lo.
 uint32_t bucket(uint64_t n, uint32_t lo) {
     uint64_t b = lo;
     while (b < n) b <<= 1;
     return (uint32_t)std::min<uint64_t>(b, 0x80000000ull);
+}
+
+// Capacities for a batch: power-of-two buckets of the sizes (so launch
+// shapes and captured graphs repeat) and learned per-grain ratios.
+int batch_caps(const emt_ctx *ctx, unsigned long long n_total, uint32_t n_views, uint32_t max_n,
+               Caps *out) {
+    Caps c{};
+    c.n_total = bucket(n_total, 1024);
+    c.n_views = bucket(n_views, 1);
+    const unsigned long long cells_cap = 4ull * c.n_total + 4097ull * c.n_views;
+    if (cells_cap >= (1ull << 31)) return EMT_ERANGE;
+    c.n_cells = (uint32_t)cells_cap;
+    c.max_view_n = std::min(c.n_total, bucket(max_n, 64));
+    c.seed_cap = std::min<unsigned long long>(
+        kSeedCapMax, std::max<unsigned long long>(
+                         4096, (unsigned long long)(ctx->seeds_per_grain * (double)c.n_total)));
+    c.cand_cap = clamp_u32(ctx->cand_per_grain * (double)c.n_total);
+    c.mem_cap = clamp_u32(ctx->mem_per_cand * (double)c.cand_cap);
+    *out = c;
+    return EMT_OK;
 }
 
 }  // namespace
@@ -602,28 +677,41 @@ int emt_create(const emt_config *cfg, emt_ctx **out) {
             return EMT_EDEVICE;
         }
     }
+    if (hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming) != hipSuccess) {
+        emt_destroy(ctx);
+        return EMT_EDEVICE;
+    }
     *out = ctx;
     return EMT_OK;
 }
 
-static int track_views_impl(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views,
-                            emt_view_out *out);
+}  // extern "C"
 
-int emt_track_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views, emt_view_out *out) {
-    const int rc = track_views_impl(ctx, views, n_views, out);
-    // return codes carry every failure: leave no sticky HIP error behind
-    (void)hipGetLastError();
-    return rc;
+namespace emt {
+
+// Device bytes a context needs for a batch of these sizes (its arenas only
+// grow, so this bounds what the batch adds to the context's holdings).
+size_t batch_bytes(const emt_ctx *ctx, unsigned long long n_total, uint32_t n_views,
+                   uint32_t max_n) {
+    Caps c{};
+    if (batch_caps(ctx, n_total, n_views, max_n, &c)) return SIZE_MAX;
+    return grain_bytes(std::max<uint32_t>(c.n_total, 1024)) + seed_bytes(c.seed_cap) +
+           cand_bytes(c.cand_cap) + mem_bytes(c.mem_cap) +
+           cell_bytes(std::max<uint32_t>(scan_words(c), 1u << 16)) +
+           view_bytes(std::max<uint32_t>(c.n_views, 64));
 }
 
-static int track_views_impl(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views,
-                            emt_view_out *out) {
+size_t held_bytes(const emt_ctx *ctx) { return ctx->held; }
+
+// First half of a call: check, size, stage and enqueue the first attempt.
+// The views (and, for host input, their grains) must stay valid until
+// finish_views returns.
+int begin_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views) {
     if (!ctx) return EMT_EINVAL;
     if (ctx->poisoned) return EMT_EDEVICE;
-    if (n_views > 0 && !out) return EMT_EINVAL;
+    if (ctx->pend.active) return EMT_EINVAL;
     int rc = check_views(&ctx->cfg, views, n_views);
     if (rc) return rc;
-    if (n_views == 0) return EMT_OK;
     if (hipSetDevice(ctx->cfg.device) != hipSuccess) {
         ctx->poisoned = true;
         return EMT_EDEVICE;
@@ -637,17 +725,7 @@ static int track_views_impl(emt_ctx *ctx, const emt_view_in *views, uint32_t n_v
         max_n = std::max(max_n, views[v].n_grains);
     }
     Caps c{};
-    c.n_total = bucket(n_total, 1024);
-    c.n_views = bucket(n_views, 1);
-    const unsigned long long cells_cap = 4ull * c.n_total + 4097ull * c.n_views;
-    if (cells_cap >= (1ull << 31)) return EMT_ERANGE;
-    c.n_cells = (uint32_t)cells_cap;
-    c.max_view_n = std::min(c.n_total, bucket(max_n, 64));
-    c.seed_cap = std::min<unsigned long long>(
-        kSeedCapMax, std::max<unsigned long long>(
-                         4096, (unsigned long long)(ctx->seeds_per_grain * (double)c.n_total)));
-    c.cand_cap = clamp_u32(ctx->cand_per_grain * (double)c.n_total);
-    c.mem_cap = clamp_u32(ctx->mem_per_cand * (double)c.cand_cap);
+    if ((rc = batch_caps(ctx, n_total, n_views, max_n, &c))) return rc;
 
     // ensure the view tables exist before filling pinned staging
     if ((rc = ensure(ctx, c))) return rc;
@@ -666,28 +744,33 @@ static int track_views_impl(emt_ctx *ctx, const emt_view_in *views, uint32_t n_v
             goff += views[v].n_grains;
         }
     }
+    fill_grids(ctx, views, n_views);
+    if ((rc = run_launch(ctx, views, n_views, c))) return rc;
+    ctx->pend.views = views;
+    ctx->pend.n_views = n_views;
+    ctx->pend.caps = c;
+    ctx->pend.active = true;
+    return EMT_OK;
+}
 
+// True once the enqueued attempt has finished on the device.
+bool views_ready(emt_ctx *ctx) {
+    return !ctx->pend.active || hipEventQuery(ctx->done) != hipErrorNotReady;
+}
+
+// Second half: wait, repair an overflow by re-running with the sizes the
+// counters report, and fill out[] with per-view slices of the results.
+int finish_views(emt_ctx *ctx, emt_view_out *out) {
+    if (!ctx || !ctx->pend.active) return EMT_EINVAL;
+    ctx->pend.active = false;
+    const emt_view_in *views = ctx->pend.views;
+    const uint32_t n_views = ctx->pend.n_views;
+    Caps c = ctx->pend.caps;
+    int rc;
     uint32_t retries = 0;
     for (int attempt = 0;; ++attempt) {
-        if ((rc = ensure(ctx, c))) return rc;
         bool overflow = false;
-        // ViewGrid staging is overwritten by the read-back: refill per attempt
-        uint32_t go = 0, co = 0;
-        for (uint32_t v = 0; v < n_views; ++v) {
-            ViewGrid &G = ctx->h_grids[v];
-            G = ViewGrid{};
-            for (int m = 0; m < 3; ++m) {
-                G.lo[m] = INT32_MAX;
-                G.hi[m] = INT32_MIN;
-            }
-            G.grain_off = go;
-            G.n = views[v].n_grains;
-            G.cell_off = co;
-            G.cell_cap = 4u * views[v].n_grains + 4096u;
-            go += G.n;
-            co += G.cell_cap + 1;
-        }
-        rc = run_once(ctx, views, n_views, c, &overflow);
+        rc = run_check(ctx, c, &overflow);
         if (rc == EMT_OK) break;
         if (!overflow) return rc;
         if (attempt + 1 >= kMaxAttempts) return EMT_EOVERFLOW;
@@ -711,6 +794,9 @@ static int track_views_impl(emt_ctx *ctx, const emt_view_in *views, uint32_t n_v
             c.mem_cap = clamp_u32(std::max((double)h.n_members * 1.125 + 1024,
                                            ctx->mem_per_cand * (double)c.cand_cap));
         }
+        if ((rc = ensure(ctx, c))) return rc;
+        fill_grids(ctx, views, n_views);
+        if ((rc = run_launch(ctx, views, n_views, c))) return rc;
     }
 
     // device-side rejections (span of device-resident views)
@@ -767,6 +853,27 @@ static int track_views_impl(emt_ctx *ctx, const emt_view_in *views, uint32_t n_v
     return EMT_OK;
 }
 
+}  // namespace emt
+
+extern "C" {
+
+int emt_track_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views, emt_view_out *out) {
+    int rc;
+    if (!ctx) {
+        rc = EMT_EINVAL;
+    } else if (n_views > 0 && !out) {
+        rc = EMT_EINVAL;
+    } else if (n_views == 0) {
+        rc = ctx->poisoned ? EMT_EDEVICE : check_views(&ctx->cfg, views, 0);
+    } else {
+        rc = begin_views(ctx, views, n_views);
+        if (rc == EMT_OK) rc = finish_views(ctx, out);
+    }
+    // return codes carry every failure: leave no sticky HIP error behind
+    (void)hipGetLastError();
+    return rc;
+}
+
 int emt_last_stats(emt_ctx *ctx, emt_call_stats *stats) {
     if (!ctx || !stats) return EMT_EINVAL;
     *stats = ctx->last;
@@ -789,6 +896,7 @@ void emt_destroy(emt_ctx *ctx) {
         if (p) (void)hipHostFree(p);
     for (int i = 0; i <= EMT_N_STAGES; ++i)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    if (ctx->done) (void)hipEventDestroy(ctx->done);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     (void)hipGetLastError();

@@ -20,7 +20,9 @@ EMT_F_STATS, EMT_F_FP64_FIT_ALWAYS, EMT_F_DEVICE_PTRS = 0x1, 0x2, 0x4
 STAGES = ("stage", "bin", "seed", "count", "members", "merge", "fit", "out")
 EMT_N_STAGES = len(STAGES)
 EXPORTS = ("emt_default_config", "emt_validate", "emt_create", "emt_track_views",
-           "emt_last_stats", "emt_destroy", "emt_strerror")
+           "emt_last_stats", "emt_destroy", "emt_strerror", "emt_server_create",
+           "emt_server_submit", "emt_server_poll", "emt_server_get_stats",
+           "emt_server_destroy")
 
 
 class EmtConfig(C.Structure):
@@ -59,6 +61,22 @@ class EmtCallStats(C.Structure):
                 ("merge_rounds", C.c_uint32), ("n_fp64_fits", C.c_uint32),
                 ("retries", C.c_uint32), ("n_views", C.c_uint32),
                 ("ms", C.c_float * EMT_N_STAGES), ("ms_total", C.c_float)]
+
+
+class EmtServed(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("view_id", C.c_uint64), ("status", C.c_int32),
+                ("n_tracks", C.c_uint32), ("n_track_grains", C.c_uint32),
+                ("batch_views", C.c_uint32), ("tracks", C.POINTER(EmtTrack)),
+                ("grains", C.POINTER(C.c_uint32)), ("stats", EmtViewStats),
+                ("t_submit_ms", C.c_double), ("t_admit_ms", C.c_double),
+                ("t_done_ms", C.c_double)]
+
+
+class EmtServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("batches", C.c_uint64),
+                ("max_batch_views_seen", C.c_uint32), ("n_pipes", C.c_uint32),
+                ("busy_ms", C.c_double), ("overlap_ms", C.c_double),
+                ("elapsed_ms", C.c_double)]
 
 
 TRACK_DTYPE = np.dtype([("seed", "<u4", (2,)), ("grain_offset", "<u4"), ("n_grains", "<u4"),
@@ -101,6 +119,18 @@ def load(path: str = LIB_PATH):
     lib.emt_destroy.restype = None
     lib.emt_strerror.argtypes = [C.c_int]
     lib.emt_strerror.restype = C.c_char_p
+    lib.emt_server_create.argtypes = [C.POINTER(EmtConfig), C.c_uint32, C.c_uint32,
+                                      C.POINTER(C.c_void_p)]
+    lib.emt_server_create.restype = C.c_int
+    lib.emt_server_submit.argtypes = [C.c_void_p, C.POINTER(EmtViewIn), C.POINTER(C.c_uint64)]
+    lib.emt_server_submit.restype = C.c_int
+    lib.emt_server_poll.argtypes = [C.c_void_p, C.POINTER(EmtServed), C.c_uint32,
+                                    C.POINTER(C.c_uint32), C.c_int32]
+    lib.emt_server_poll.restype = C.c_int
+    lib.emt_server_get_stats.argtypes = [C.c_void_p, C.POINTER(EmtServerStats)]
+    lib.emt_server_get_stats.restype = C.c_int
+    lib.emt_server_destroy.argtypes = [C.c_void_p]
+    lib.emt_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -157,6 +187,17 @@ def emt_create(cfg: EmtConfig):
     return h
 
 
+def _result(nt: int, ng: int, tracks_p, grains_p):
+    if nt:
+        raw = np.ctypeslib.as_array(C.cast(tracks_p, C.POINTER(C.c_uint8)),
+                                    shape=(nt * TRACK_DTYPE.itemsize,))
+        tracks = raw.view(TRACK_DTYPE).copy()
+    else:
+        tracks = np.zeros(0, TRACK_DTYPE)
+    grains = np.ctypeslib.as_array(grains_p, shape=(ng,)).copy() if ng else np.zeros(0, np.uint32)
+    return tracks, grains
+
+
 def emt_track_views(ctx, views, device_ptrs: bool = False):
     """Track a list of views; returns one dict per view with ``tracks`` (a
     numpy array of TRACK_DTYPE), ``grains`` (uint32 input indices) and
@@ -171,15 +212,7 @@ def emt_track_views(ctx, views, device_ptrs: bool = False):
     res = []
     for i in range(len(views)):
         o = out[i]
-        nt, ng = o.n_tracks, o.n_track_grains
-        if nt:
-            raw = np.ctypeslib.as_array(C.cast(o.tracks, C.POINTER(C.c_uint8)),
-                                        shape=(nt * TRACK_DTYPE.itemsize,))
-            tracks = raw.view(TRACK_DTYPE).copy()
-        else:
-            tracks = np.zeros(0, TRACK_DTYPE)
-        grains = (np.ctypeslib.as_array(o.grains, shape=(ng,)).copy() if ng
-                  else np.zeros(0, np.uint32))
+        tracks, grains = _result(o.n_tracks, o.n_track_grains, o.tracks, o.grains)
         res.append({"view_id": int(o.view_id), "tracks": tracks, "grains": grains,
                     "n_seeds": int(o.stats.n_seeds),
                     "n_candidates": int(o.stats.n_candidates)})
@@ -219,6 +252,76 @@ class Tracker:
         if self.ctx is not None:
             emt_destroy(self.ctx)
             self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The served form: ``submit`` views as they arrive, ``poll`` finished
+    ones. Wraps emt_server_* (argument marshalling only)."""
+
+    def __init__(self, n_pipes: int = 2, max_batch_views: int = 64, **cfg):
+        self.cfg = emt_default_config(**cfg)
+        h = C.c_void_p()
+        rc = load().emt_server_create(C.byref(self.cfg), n_pipes, max_batch_views, C.byref(h))
+        if rc != EMT_OK:
+            raise EmtError(rc, "emt_server_create")
+        self.h = h
+        self._buf = (EmtServed * 256)()
+
+    def submit(self, xyz, view_id: int = 0) -> int:
+        a = np.ascontiguousarray(np.asarray(xyz, dtype=np.int32).reshape(-1, 3))
+        v = EmtViewIn()
+        v.xyz = a.ctypes.data if len(a) else None
+        v.n_grains = len(a)
+        v.view_id = view_id
+        t = C.c_uint64()
+        rc = load().emt_server_submit(self.h, C.byref(v), C.byref(t))
+        if rc != EMT_OK:
+            raise EmtError(rc, "emt_server_submit")
+        return int(t.value)
+
+    def poll(self, wait_ms: int = 0, max_out: int = 256) -> list:
+        """Finished views as dicts (tracks and grains copied out)."""
+        max_out = min(max_out, len(self._buf))
+        n = C.c_uint32()
+        rc = load().emt_server_poll(self.h, self._buf, max_out, C.byref(n), wait_ms)
+        res = []
+        for i in range(n.value):
+            o = self._buf[i]
+            tracks, grains = _result(o.n_tracks, o.n_track_grains, o.tracks, o.grains)
+            res.append({"ticket": int(o.ticket), "view_id": int(o.view_id),
+                        "status": int(o.status), "batch_views": int(o.batch_views),
+                        "tracks": tracks, "grains": grains,
+                        "n_seeds": int(o.stats.n_seeds),
+                        "n_candidates": int(o.stats.n_candidates),
+                        "t_submit_ms": o.t_submit_ms, "t_admit_ms": o.t_admit_ms,
+                        "t_done_ms": o.t_done_ms})
+        if rc != EMT_OK:
+            raise EmtError(rc, "emt_server_poll")
+        return res
+
+    def stats(self) -> dict:
+        st = EmtServerStats()
+        rc = load().emt_server_get_stats(self.h, C.byref(st))
+        if rc != EMT_OK:
+            raise EmtError(rc, "emt_server_get_stats")
+        return {k: getattr(st, k) for k, _ in EmtServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            load().emt_server_destroy(self.h)
+            self.h = None
 
     def __enter__(self):
         return self

@@ -47,8 +47,11 @@ def test_struct_layout_matches_header(emt):
 #define O(t, f) printf(#t "." #f " %zu\n", offsetof(t, f));
 int main(void) {
   S(emt_config) S(emt_view_in) S(emt_track) S(emt_view_stats) S(emt_view_out) S(emt_call_stats)
+  S(emt_served) S(emt_server_stats)
   O(emt_config, hbm_budget) O(emt_config, stream) O(emt_track, slope) O(emt_track, t_end)
   O(emt_view_out, tracks) O(emt_view_out, stats) O(emt_call_stats, ms) O(emt_call_stats, ms_total)
+  O(emt_served, tracks) O(emt_served, stats) O(emt_served, t_done_ms)
+  O(emt_server_stats, busy_ms) O(emt_server_stats, elapsed_ms)
   return 0;
 }
 """
@@ -71,6 +74,12 @@ int main(void) {
         "emt_view_out.stats": emt.EmtViewOut.stats.offset,
         "emt_call_stats.ms": emt.EmtCallStats.ms.offset,
         "emt_call_stats.ms_total": emt.EmtCallStats.ms_total.offset,
+        "emt_served": C.sizeof(emt.EmtServed), "emt_server_stats": C.sizeof(emt.EmtServerStats),
+        "emt_served.tracks": emt.EmtServed.tracks.offset,
+        "emt_served.stats": emt.EmtServed.stats.offset,
+        "emt_served.t_done_ms": emt.EmtServed.t_done_ms.offset,
+        "emt_server_stats.busy_ms": emt.EmtServerStats.busy_ms.offset,
+        "emt_server_stats.elapsed_ms": emt.EmtServerStats.elapsed_ms.offset,
     }
     for k, v in exp.items():
         assert int(got[k]) == v, (k, got[k], v)
@@ -133,3 +142,24 @@ def test_create_and_track_reject_null_without_device(emt):
     assert lib.emt_track_views(None, None, 0, None) == -1
     assert lib.emt_last_stats(None, None) == -1
     lib.emt_destroy(None)
+
+
+def test_server_rejects_bad_arguments_without_device(emt):
+    lib = emt.load()
+    cfg = emt.emt_default_config()
+    h = C.c_void_p()
+    assert lib.emt_server_create(None, 2, 8, C.byref(h)) == -1
+    assert lib.emt_server_create(C.byref(cfg), 2, 8, None) == -1
+    assert lib.emt_server_create(C.byref(cfg), 0, 8, C.byref(h)) == -1
+    assert lib.emt_server_create(C.byref(cfg), 9, 8, C.byref(h)) == -1
+    assert lib.emt_server_create(C.byref(cfg), 2, 0, C.byref(h)) == -1
+    dev = emt.emt_default_config(flags=emt.EMT_F_DEVICE_PTRS)
+    assert lib.emt_server_create(C.byref(dev), 2, 8, C.byref(h)) == -1
+    bad = emt.emt_default_config(seed_dist=0)
+    assert lib.emt_server_create(C.byref(bad), 2, 8, C.byref(h)) == -2
+    assert h.value is None
+    n = C.c_uint32()
+    assert lib.emt_server_submit(None, None, None) == -1
+    assert lib.emt_server_poll(None, None, 0, C.byref(n), 0) == -1
+    assert lib.emt_server_get_stats(None, None) == -1
+    lib.emt_server_destroy(None)
