@@ -33,12 +33,18 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # multiplies, 2 adds), one compare.
 OPS_PER_TEST = 18
 HBM_PEAK_GBS = 8000.0
-COUNT_KERNEL_SRC = os.path.join(ROOT, "paper_1311_5334_amd", "csrc", "kernels.hip")
+# the counting kernel's code and the cell table that shapes its work
+COUNT_KERNEL_SRCS = [os.path.join(ROOT, "paper_1311_5334_amd", "csrc", f)
+                     for f in ("kernels.hip", "cell_table.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "count_traffic.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "count_valu.json")
 
 
 def kernel_source_hash() -> str:
-    return hashlib.sha256(open(COUNT_KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in COUNT_KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_for_current_kernel(per_launch_tests: float):
@@ -51,6 +57,18 @@ def traffic_for_current_kernel(per_launch_tests: float):
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def valu_counters_for_current_kernel():
+    """The counting kernel's VALU issue rate and lane use from the committed
+    PMC summary, only if it was taken on the current kernel source."""
+    try:
+        rec = json.load(open(VALU_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return {k: rec[k] for k in ("valu_issue_frac", "lane_util", "lane_ops_frac_of_peak")}
 
 
 def cpu_baseline(view, max_seconds: float = 30.0):
@@ -273,7 +291,8 @@ def main() -> int:
         "roofline": {"kernel": "k_count", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(peak, 2), "unit": "Tops/s",
                      "frac": round(achieved / peak, 4),
-                     "traffic": traffic_for_current_kernel(tests)},
+                     "traffic": traffic_for_current_kernel(tests),
+                     "counters": valu_counters_for_current_kernel()},
     }
     forms = {}
     for f in [x for x in args.forms.split(",") if x]:

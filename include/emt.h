@@ -63,10 +63,13 @@ extern "C" {
  *   tol_radius  r in units (default 50 = 0.5 um); 0 <= r < R. Inclusive.
  *   min_grains  n_min (default 8); 2 <= n_min < 2^20. Applied to the count
  *               and again after exclusive association.
- *   cell        edge of a hash cell along x, y, z in units (0 = library
- *               choice: 250, 750, 500). Cells only steer the work (paper
- *               Sec. 3 footnote), never the result; the library widens them
- *               if a view would need more than 4N + 4096 cells.
+ *   cell        edge of a hash cell along x, y, z in units. All three 0:
+ *               the library picks them per view from the view's grain
+ *               density (a table written by the project's autotuner); else
+ *               the given edges, with 250, 750, 500 for an axis left at 0.
+ *               Cells only steer the work (paper Sec. 3 footnote), never the
+ *               result; the library widens them if a view would need more
+ *               than 4N + 4096 cells.
  *   device      HIP device ordinal.
  *   flags       EMT_F_* bits.
  *   hbm_budget  device bytes the context may hold (0 = 80 % of free memory).

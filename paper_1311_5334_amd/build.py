@@ -19,7 +19,7 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
          # no packed FP32 instructions anywhere in device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-I" + INCLUDE, "-I" + CSRC]
+         "-Wall", "-Wshadow", "-I" + INCLUDE, "-I" + CSRC]
 
 
 def _compile(src: str) -> str:

@@ -16,6 +16,7 @@
 #include <new>
 #include <vector>
 
+#include "cell_table.h"
 #include "emt_dev.h"
 #include "emt_host.h"
 
@@ -24,8 +25,9 @@ using namespace emt;
 namespace {
 
 constexpr uint32_t kKnownFlags = EMT_F_STATS | EMT_F_FP64_FIT_ALWAYS | EMT_F_DEVICE_PTRS;
-// Default cell edges (units): short along x, where a cell row is one
-// contiguous run, and about the paper's 7.5 um hash cell across it.
+// Cell edges (units) for an axis left at 0 when the others are given:
+// short along x, where a cell row is one contiguous run, and about the
+// paper's 7.5 um hash cell across it.
 constexpr int kDefaultCell[3] = {250, 750, 500};
 constexpr int kMaxAttempts = 4;
 // seeds of one call are indexed by uint32 and scanned in uint32
@@ -633,14 +635,20 @@ int emt_create(const emt_config *cfg, emt_ctx **out) {
     ctx->P.r = cfg->tol_radius;
     ctx->P.n_min = cfg->min_grains;
     ctx->P.count_lanes = 1;
+    // cell edges: per view from the tuned density table when none is given
+    ctx->P.auto_cells = (cfg->cell[0] || cfg->cell[1] || cfg->cell[2]) ? 0 : 1;
     for (int m = 0; m < 3; ++m) ctx->P.cell_req[m] = cfg->cell[m] ? cfg->cell[m] : kDefaultCell[m];
+    for (int b = 0; b < kCellBuckets; ++b)
+        for (int m = 0; m < 3; ++m) ctx->P.cell_tab[b][m] = kTunedCells[b][m];
     ctx->P.flags = cfg->flags;
     // Tuning hooks: cell edges "x,y,z" in units, and lanes per seed line.
     if (const char *e = std::getenv("EMT_CELL")) {
         int v[3];
         if (std::sscanf(e, "%d,%d,%d", &v[0], &v[1], &v[2]) == 3 && v[0] > 0 && v[1] > 0 &&
-            v[2] > 0 && v[0] <= kSpanMax && v[1] <= kSpanMax && v[2] <= kSpanMax)
+            v[2] > 0 && v[0] <= kSpanMax && v[1] <= kSpanMax && v[2] <= kSpanMax) {
             for (int m = 0; m < 3; ++m) ctx->P.cell_req[m] = v[m];
+            ctx->P.auto_cells = 0;
+        }
     }
     if (const char *e = std::getenv("EMT_COUNT_LANES")) {
         const int k = std::atoi(e);

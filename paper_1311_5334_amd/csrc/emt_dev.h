@@ -40,10 +40,17 @@ struct BatchDesc {
     uint32_t n_cells_m1;  // n_cells - 1 (scan length of the cell table)
 };
 
+// Cell edges by grain density: bucket b holds views with at least
+// kCellEdge0 * 2^(b-1) grains per 1000 um^3 (b = 0: below kCellEdge0).
+constexpr int kCellBuckets = 8;
+constexpr double kCellEdge0 = 0.75;
+
 struct Params {
     int32_t R, r, n_min, count_lanes;
-    int32_t cell_req[3];
+    int32_t cell_req[3];  // fixed cell edges, used when auto_cells == 0
     uint32_t flags;
+    int32_t auto_cells;   // 1: per view from cell_tab by density
+    int32_t cell_tab[kCellBuckets][3];
 };
 
 // Device counters of one call. Totals keep counting past capacities so the

@@ -29,29 +29,6 @@ __device__ __forceinline__ unsigned long long lanes_below() {
     return (1ull << lane_id()) - 1ull;
 }
 
-// Reserve one slot per lane with pred among the active lanes of the wave;
-// a single atomic per wave.
-__device__ __forceinline__ unsigned long long wave_append(
-    bool pred, unsigned long long *counter) {
-    const unsigned long long mask = __ballot(pred);
-    if (mask == 0) return 0;
-    const int leader = __ffsll((long long)mask) - 1;
-    unsigned long long base = 0;
-    if (lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
-    base = __shfl(base, leader);
-    return base + (unsigned long long)__popcll(mask & lanes_below());
-}
-
-__device__ __forceinline__ uint32_t wave_append32(bool pred, uint32_t *counter) {
-    const unsigned long long mask = __ballot(pred);
-    if (mask == 0) return 0;
-    const int leader = __ffsll((long long)mask) - 1;
-    uint32_t base = 0;
-    if (lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
-    base = __shfl(base, leader);
-    return base + (uint32_t)__popcll(mask & lanes_below());
-}
-
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -248,8 +225,20 @@ __global__ void k_grid(ViewGrid *grids, const BatchDesc *desc, Params P) {
         }
         span[m] = (long long)G.hi[m] - (long long)G.lo[m];
         if (span[m] > kSpanMax) G.err = 1;
-        G.cell[m] = P.cell_req[m];
     }
+    // cell edges: fixed, or by the view's grain density (bounding box)
+    int b = 0;
+    if (P.auto_cells) {
+        const double vol_um3 = (double)(span[0] + 1) * (double)(span[1] + 1) *
+                               (double)(span[2] + 1) * 1e-6;
+        const double per_1000 = 1000.0 * (double)G.n / vol_um3;
+        double edge = kCellEdge0;
+        while (b < kCellBuckets - 1 && per_1000 >= edge) {
+            ++b;
+            edge *= 2.0;
+        }
+    }
+    for (int m = 0; m < 3; ++m) G.cell[m] = P.auto_cells ? P.cell_tab[b][m] : P.cell_req[m];
     if (G.err) {
         for (int m = 0; m < 3; ++m) {
             G.cell[m] = 1;
@@ -477,25 +466,23 @@ struct Pencil {
 // component of c is below 2^31 and the wrapped result equals it. |c|^2 is
 // compared in FP32 with a relative guard band of 2^-20 (the FP32 sum of
 // squares is within 5 * 2^-24 of exact); inside the band the test is redone
-// in int64.
+// in int64, with the threshold r^2 |d|^2 formed there.
 struct LineTest {
     uint32_t ex, ey, ez;
     float tlo, thi;
-    long long T;
 
     __device__ __forceinline__ void init(int4 gi, int dx, int dy, int dz, int r) {
         ex = (uint32_t)__mul24(gi.y, dz) - (uint32_t)__mul24(gi.z, dy);
         ey = (uint32_t)__mul24(gi.z, dx) - (uint32_t)__mul24(gi.x, dz);
         ez = (uint32_t)__mul24(gi.x, dy) - (uint32_t)__mul24(gi.y, dx);
         const long long D = (long long)dx * dx + (long long)dy * dy + (long long)dz * dz;
-        T = (long long)r * r * D;
-        const float tf = (float)T;
+        const float tf = (float)((long long)r * r * D);
         tlo = tf * (1.0f - 0x1p-20f);
         thi = tf * (1.0f + 0x1p-20f);
     }
 };
 
-__device__ __forceinline__ bool cyl_hit(int4 h, int4 A, int4 B, const long long *T) {
+__device__ __forceinline__ bool cyl_hit(int4 h, int4 A, int4 B, int tol_r) {
     // A = (dx, dy, dz, tlo), B = (ex, ey, ez, thi)
     const int c0 = (int)((uint32_t)__mul24(h.y, A.z) - (uint32_t)__mul24(h.z, A.y) - (uint32_t)B.x);
     const int c1 = (int)((uint32_t)__mul24(h.z, A.x) - (uint32_t)__mul24(h.x, A.z) - (uint32_t)B.y);
@@ -505,7 +492,8 @@ __device__ __forceinline__ bool cyl_hit(int4 h, int4 A, int4 B, const long long 
     if (fc <= __int_as_float(A.w)) return true;
     if (fc > __int_as_float(B.w)) return false;
     const long long cc = (long long)c0 * c0 + (long long)c1 * c1 + (long long)c2 * c2;
-    return cc <= *T;
+    const long long D = (long long)A.x * A.x + (long long)A.y * A.y + (long long)A.z * A.z;
+    return cc <= (long long)tol_r * tol_r * D;
 }
 
 // ----------------------------------------------------------------- seeds
@@ -609,7 +597,6 @@ constexpr int kMaskWords = kSlotCap / 64;
 struct QueueLds {
     int4 pa[64];  // dx, dy, dz, tlo
     int4 pb[64];  // ex, ey, ez, thi
-    long long T[64];
     uint32_t cnt[64];
     uint32_t out_off[64];
     uint32_t ncap[64];
@@ -650,7 +637,7 @@ __device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t x) {
 }
 
 template <bool kMembers>
-__device__ __forceinline__ void flush_queue(QueueLds &Q, uint32_t qn, const int4 *__restrict__ sg,
+__device__ __forceinline__ void flush_queue(QueueLds &Q, uint32_t qn, int tol_r, const int4 *__restrict__ sg,
                                             uint32_t *__restrict__ members, int lane) {
     wave_lds_sync();
     const uint32_t nw = (qn + 63) >> 6;
@@ -671,7 +658,7 @@ __device__ __forceinline__ void flush_queue(QueueLds &Q, uint32_t qn, const int4
             const uint32_t kk = Q.run_k[r] + (s - (tag & 0xffffu));
             const uint32_t sl = tag >> 16;
             const int4 h = sg[kk];
-            if (cyl_hit(h, Q.pa[sl], Q.pb[sl], &Q.T[sl])) {
+            if (cyl_hit(h, Q.pa[sl], Q.pb[sl], tol_r)) {
                 const uint32_t pos = atomicAdd(&Q.cnt[sl], 1u);
                 if (kMembers && pos < Q.ncap[sl]) members[Q.out_off[sl] + pos] = kk;
             }
@@ -727,7 +714,6 @@ __global__ void __launch_bounds__(kBlock) k_lines(DevPtrs d, Caps c, Params P) {
         if (sub == 0) {
             Q.pa[slot] = make_int4(dx, dy, dz, __float_as_int(L.tlo));
             Q.pb[slot] = make_int4((int)L.ex, (int)L.ey, (int)L.ez, __float_as_int(L.thi));
-            Q.T[slot] = L.T;
             Q.cnt[slot] = 0;
             Q.out_off[slot] = off;
             Q.ncap[slot] = ncap;
@@ -796,12 +782,12 @@ __global__ void __launch_bounds__(kBlock) k_lines(DevPtrs d, Caps c, Params P) {
             nr += tot >> 16;
             tests += mine;
             if (qn > (uint32_t)(kSlotCap - 64 * kLaneCap) || nr > (uint32_t)(kRunCap - 256)) {
-                flush_queue<kMembers>(Q, qn, d.sg, d.members, lane);
+                flush_queue<kMembers>(Q, qn, P.r, d.sg, d.members, lane);
                 qn = 0;
                 nr = 0;
             }
         }
-        if (qn) flush_queue<kMembers>(Q, qn, d.sg, d.members, lane);
+        if (qn) flush_queue<kMembers>(Q, qn, P.r, d.sg, d.members, lane);
         wave_lds_sync();
         const uint32_t n = Q.cnt[slot];
         if (sub != 0) {
@@ -838,17 +824,30 @@ __global__ void __launch_bounds__(kBlock) k_lines(DevPtrs d, Caps c, Params P) {
 // time is the sum of its lines' work rather than a multiple of the longest
 // one. Hit counts of a closed slot are final after the next queue flush,
 // which writes them out and frees the slot.
+#ifndef EMT_COUNT_SLOT_CAP
+#define EMT_COUNT_SLOT_CAP 4096
+#endif
+#ifndef EMT_COUNT_RUN_CAP
+#define EMT_COUNT_RUN_CAP 512
+#endif
+#ifndef EMT_COUNT_LANE_CAP
+#define EMT_COUNT_LANE_CAP 32
+#endif
+#ifndef EMT_CHUNK_SEEDS
+#define EMT_CHUNK_SEEDS 64
+#endif
 constexpr int kCountSlots = 128;
-constexpr int kCountSlotCap = 1024;
-constexpr int kCountRunCap = 512;
-constexpr int kCountLaneCap = 8;
+constexpr int kCountSlotCap = EMT_COUNT_SLOT_CAP;  // queued tests per wave
+constexpr int kCountRunCap = EMT_COUNT_RUN_CAP;    // queued runs per wave
+constexpr int kCountLaneCap = EMT_COUNT_LANE_CAP;  // tests a lane queues per step
 constexpr int kCountMaskWords = kCountSlotCap / 64;
-constexpr int kChunkSeeds = 64;
+constexpr int kChunkSeeds = EMT_CHUNK_SEEDS;
+static_assert(kCountSlotCap > 64 * kCountLaneCap, "a step must fit the slot queue");
+static_assert(kCountMaskWords <= 64, "one mask word per lane");
 
 struct CountLds {
     int4 pa[kCountSlots];
     int4 pb[kCountSlots];
-    long long T[kCountSlots];
     uint32_t cnt[kCountSlots];
     unsigned long long mask[kCountMaskWords];
     uint32_t before[kCountMaskWords];
@@ -856,7 +855,7 @@ struct CountLds {
     uint32_t run_tag[kCountRunCap];  // first queue slot | seed slot << 16
 };
 
-__device__ __forceinline__ void count_flush(CountLds &Q, uint32_t qn, const int4 *__restrict__ sg,
+__device__ __forceinline__ void count_flush(CountLds &Q, uint32_t qn, int tol_r, const int4 *__restrict__ sg,
                                             int lane) {
     wave_lds_sync();
     const uint32_t nw = (qn + 63) >> 6;
@@ -876,7 +875,7 @@ __device__ __forceinline__ void count_flush(CountLds &Q, uint32_t qn, const int4
             const uint32_t kk = Q.run_k[r] + (s - (tag & 0xffffu));
             const uint32_t sl = tag >> 16;
             const int4 h = sg[kk];
-            if (cyl_hit(h, Q.pa[sl], Q.pb[sl], &Q.T[sl])) atomicAdd(&Q.cnt[sl], 1u);
+            if (cyl_hit(h, Q.pa[sl], Q.pb[sl], tol_r)) atomicAdd(&Q.cnt[sl], 1u);
         }
     }
     wave_lds_sync();
@@ -930,7 +929,6 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
                 L.init(gi, dx, dy, dz, P.r);
                 Q.pa[cur] = make_int4(dx, dy, dz, __float_as_int(L.tlo));
                 Q.pb[cur] = make_int4((int)L.ex, (int)L.ey, (int)L.ez, __float_as_int(L.thi));
-                Q.T[cur] = L.T;
                 Q.cnt[cur] = 0;
                 W.init(&d.grids[v], gi, dx, dy, dz, P.r, true, 0, 1);
                 have = true;
@@ -1004,7 +1002,7 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
             const bool all_done = __ballot(have) == 0 && next >= end && !more;
             if (all_done || qn > (uint32_t)(kCountSlotCap - 64 * kCountLaneCap) ||
                 nr > (uint32_t)(kCountRunCap - 256) || n_blocked > 16) {
-                if (qn) count_flush(Q, qn, d.sg, lane);
+                if (qn) count_flush(Q, qn, P.r, d.sg, lane);
                 qn = 0;
                 nr = 0;
                 // every closed slot is final now
@@ -1630,7 +1628,16 @@ uint32_t blocks_for(unsigned long long n, uint32_t max_blocks) {
     return (uint32_t)(b < max_blocks ? b : max_blocks);
 }
 
-constexpr uint32_t kPersistentBlocks = 2048;  // 8 blocks of 4 waves per CU on 256 CUs
+#ifndef EMT_PERSISTENT_BLOCKS
+#define EMT_PERSISTENT_BLOCKS 2048
+#endif
+constexpr uint32_t kPersistentBlocks = EMT_PERSISTENT_BLOCKS;  // 8 blocks of 4 waves per CU
+#ifndef EMT_COUNT_BLOCKS
+#define EMT_COUNT_BLOCKS 1024
+#endif
+// the counting kernel's grid: one resident generation (4 workgroups per CU,
+// bound by its LDS and registers), so no workgroup waits for another's slot
+constexpr uint32_t kCountBlocks = EMT_COUNT_BLOCKS;
 
 }  // namespace
 
@@ -1668,7 +1675,7 @@ void launch_count(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t 
         k_lines<false, 1><<<nb, kBlock, 0, s>>>(d, c, P);
         return;
     }
-    k_count<<<kPersistentBlocks, kBlock, 0, s>>>(d, c, P);
+    k_count<<<kCountBlocks, kBlock, 0, s>>>(d, c, P);
 }
 
 void launch_candidates(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {

@@ -255,6 +255,22 @@ def make_c5(index: int = 0) -> View:
     return _assemble(rng, box, segs, 10e-3, "c5", seed)
 
 
+def make_density_view(seed: int, per_1000_um3: float, side_um: float = 200.0) -> View:
+    """A c4-like view (2449 tracks/mm^2, 20 % stopping) whose fog is chosen so
+    that the whole view holds about per_1000_um3 grains per 1000 um^3; the
+    cell autotuner sweeps these. Track grains alone may exceed the target at
+    low densities; then there is no fog."""
+    rng = _rng(seed)
+    box = np.array([side_um, side_um, THICKNESS_UM])
+    n_tracks = int(round(2449.0 * side_um * side_um * 1e-6))
+    segs = _tracks_mixed(rng, box, n_tracks)
+    track_grains = sum(0.3 * float(np.linalg.norm(np.asarray(b) - np.asarray(a)))
+                       for a, b, _d in segs)
+    vol = float(box.prod())
+    fog = max(0.0, per_1000_um3 * 1e-3 * vol - track_grains) / vol
+    return _assemble(rng, box, segs, fog, "density", seed)
+
+
 MAKERS = {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c4": make_c4, "c5": make_c5}
 
 

@@ -332,3 +332,14 @@ def test_config4_mixed_sizes_match_oracle(emt, oracle_mod):
                 continue
             _say(f"c4 view {i}: {v.n} grains")
             assert_view_parity(v.xyz, t([v.xyz])[0], oracle_mod.track_view(v.xyz))
+
+
+def test_auto_cells_match_fixed_cells(emt):
+    """Per-view cells picked by density never change a result."""
+    views = [synth.make_c3(i).xyz for i in range(6)] + [synth.make_c1(3).xyz]
+    with emt.Tracker(device=0) as auto, emt.Tracker(device=0, cell=(250, 750, 500)) as fixed, \
+            emt.Tracker(device=0, cell=(400, 0, 0)) as partial:
+        a, b, c = auto(views), fixed(views), partial(views)
+    for x, y, z in zip(a, b, c):
+        assert x["tracks"].tobytes() == y["tracks"].tobytes() == z["tracks"].tobytes()
+        assert np.array_equal(x["grains"], y["grains"]) and np.array_equal(x["grains"], z["grains"])
