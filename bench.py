@@ -122,7 +122,8 @@ def measure_batch(emt, torch, views, calls: int, warmup: int) -> dict:
 
 
 def measure_served(emt, views, n_req: int, warmup: int, batch: int = 16,
-                   fracs=(0.5, 0.9), seed: int = 0x5E4FE) -> dict:
+                   fracs=(0.5, 0.9), seed: int = 0x5E4FE, n_pipes: int = 2,
+                   max_batch: int = 64) -> dict:
     """The served form on a pool of c4 views (host arrays, as a microscope
     hands them over). First the batched capacity mu_b (views/s through
     emt_track_views, batch views per call) and the plain one-view-per-call
@@ -162,7 +163,7 @@ def measure_served(emt, views, n_req: int, warmup: int, batch: int = 16,
         total = n_req + warmup
         pick = rng.integers(0, len(xyzs), total)
         gaps = rng.exponential(1.0 / lam, total)
-        with emt.Server(n_pipes=2, max_batch_views=64, device=0) as srv:
+        with emt.Server(n_pipes=n_pipes, max_batch_views=max_batch, device=0) as srv:
             def feed():
                 t_next = time.perf_counter()
                 for k in range(total):

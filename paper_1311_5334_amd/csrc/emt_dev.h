@@ -42,6 +42,7 @@ struct BatchDesc {
 
 // Cell edges by grain density: bucket b holds views with at least
 // kCellEdge0 * 2^(b-1) grains per 1000 um^3 (b = 0: below kCellEdge0).
+constexpr int kGrabWords = 8 * 16;  // one counter per XCD, 64 B apart
 constexpr int kCellBuckets = 8;
 constexpr double kCellEdge0 = 0.75;
 
@@ -125,7 +126,8 @@ struct DevPtrs {
     uint32_t *mcount;     // cand_cap
     uint8_t *used;        // N
     unsigned long long *owner;  // N
-    uint32_t *undecided;  // per merge round: nonzero if candidates stay undecided
+    uint32_t *undecided;  // per merge round: candidates it left undecided
+    uint32_t *grab;       // kGrabWords: seed-range counters of the counting kernel
     uint32_t *act;        // cand_cap: undecided candidates handed to the tail
     uint32_t *act2;       // cand_cap
     uint32_t *acc;        // cand_cap

@@ -162,13 +162,14 @@ void scan_excl(const uint32_t *in, const uint32_t *n_dev, uint32_t n_cap, uint32
 __global__ void __launch_bounds__(kBlock) k_zero(Counters *cnt, unsigned long long *view_seeds,
                                                  uint32_t *view_cand, uint32_t *view_ntr,
                                                  uint32_t *view_cursor, uint32_t *cell_count,
-                                                 const BatchDesc *desc) {
+                                                 uint32_t *grab, const BatchDesc *desc) {
     const uint32_t tid = grid_tid();
     const uint32_t n_views = desc->n_views, n_cells = desc->n_cells;
     if (tid == 0) {
         Counters z = {};
         *cnt = z;
     }
+    if (tid < kGrabWords) grab[tid] = 0;
     for (uint32_t v = tid; v < n_views; v += grid_threads()) {
         view_seeds[v] = 0;
         view_cand[v] = 0;
@@ -833,6 +834,9 @@ __global__ void __launch_bounds__(kBlock) k_lines(DevPtrs d, Caps c, Params P) {
 #ifndef EMT_COUNT_LANE_CAP
 #define EMT_COUNT_LANE_CAP 32
 #endif
+#ifndef EMT_DYN_MIN_SEEDS
+#define EMT_DYN_MIN_SEEDS 8000000
+#endif
 #ifndef EMT_CHUNK_SEEDS
 #define EMT_CHUNK_SEEDS 64
 #endif
@@ -883,6 +887,34 @@ __device__ __forceinline__ void count_flush(CountLds &Q, uint32_t qn, int tol_r,
     wave_lds_sync();
 }
 
+// Next grab of seeds for the calling wave: its own XCD's range first, then
+// the others. grab[16 x] is range x's offset counter. Returns false when
+// every range is used up. Wave-uniform.
+__device__ __forceinline__ bool count_grab(uint32_t *grab, uint32_t xcd, uint32_t per,
+                                           uint32_t n_items, uint32_t wpx, uint32_t &next,
+                                           uint32_t &end) {
+    uint32_t s = 0xffffffffu, e = 0;
+    if (lane_id() == 0) {
+        for (uint32_t t = 0; t < 8; ++t) {
+            const uint32_t x = (xcd + t) & 7u;
+            const uint32_t lo = min(n_items, x * per), hi = min(n_items, x * per + per);
+            uint32_t *ctr = grab + 16 * x;
+            const uint32_t cur = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (cur >= hi - lo) continue;
+            uint32_t g = (hi - lo - cur) / (4u * wpx);
+            g = min(4096u, max(64u, (g + 63u) & ~63u));
+            const uint32_t at = atomicAdd(ctr, g);
+            if (at >= hi - lo) continue;
+            s = lo + at;
+            e = min(hi, s + g);
+            break;
+        }
+    }
+    next = (uint32_t)__shfl((int)s, 0);
+    end = (uint32_t)__shfl((int)e, 0);
+    return next != 0xffffffffu;
+}
+
 __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
     __shared__ CountLds sQ[kWaves];
     const int lane = lane_id();
@@ -891,12 +923,24 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
     const uint32_t n_items = (uint32_t)(ns < c.seed_cap ? ns : c.seed_cap);
     if (lane < kCountMaskWords) Q.mask[lane] = 0ull;
     wave_lds_sync();
-    const uint32_t gw = grid_tid() >> 6, nwv = grid_threads() >> 6;
     unsigned long long tests = 0, hits = 0;
-    // this wave's chunks: gw, gw + nwv, gw + 2 nwv, ... of kChunkSeeds seeds;
-    // lanes move on to the next chunk as soon as the current one is taken
+    // Which seeds a wave counts. Few seeds (one view or so, whose grains fit
+    // in L2): wave gw takes chunks gw, gw + nwv, gw + 2 nwv, ... of
+    // kChunkSeeds seeds. Many seeds: they are split into eight ranges, one
+    // per XCD (workgroups are dealt to the XCDs in turn); a wave takes grabs
+    // from its own XCD's range, so that XCD's L2 holds the grains of those
+    // views only, and moves on to the other ranges when its own is used up;
+    // grabs shrink as a range empties, so the waves finish together. (Grabs
+    // cost a device-scope atomic each, too many for a single view.)
+    const bool dyn = n_items > (uint32_t)EMT_DYN_MIN_SEEDS;
+    const uint32_t gw = grid_tid() >> 6, nwv = grid_threads() >> 6;
+    const uint32_t xcd = blockIdx.x & 7u;
+    const uint32_t per = ((n_items + 7u) / 8u + 63u) & ~63u;
+    const uint32_t wpx = (gridDim.x >> 3) * kWaves;
     uint32_t chunk = gw * kChunkSeeds;
-    uint32_t next = min(chunk, n_items), end = min(n_items, chunk + kChunkSeeds);
+    uint32_t next = dyn ? 0u : min(chunk, n_items);
+    uint32_t end = dyn ? 0u : min(n_items, chunk + kChunkSeeds);
+    bool more = true;
     bool have = false;
     bool pend0 = false, pend1 = false;  // slot closed, count not yet written
     uint32_t idx0 = 0, idx1 = 0;        // seed index held by each slot
@@ -907,10 +951,16 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
     uint32_t qn = 0, nr = 0;
     for (;;) {
         {
-            if (next >= end && chunk + nwv * kChunkSeeds < n_items) {
-                chunk += nwv * kChunkSeeds;
-                next = chunk;
-                end = min(n_items, chunk + kChunkSeeds);
+            if (dyn) {
+                if (next >= end && more) more = count_grab(d.grab, xcd, per, n_items, wpx, next, end);
+            } else {
+                more = chunk + nwv * kChunkSeeds < n_items;
+                if (next >= end && more) {
+                    chunk += nwv * kChunkSeeds;
+                    next = chunk;
+                    end = min(n_items, chunk + kChunkSeeds);
+                    more = chunk + nwv * kChunkSeeds < n_items;
+                }
             }
             // take the next seeds into free slots
             const bool want = !have && !(pend0 && pend1);
@@ -998,7 +1048,7 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
             }
             const bool blocked = !have && pend0 && pend1;
             const uint32_t n_blocked = (uint32_t)__popcll(__ballot(blocked));
-            const bool more = chunk + nwv * kChunkSeeds < n_items;
+
             const bool all_done = __ballot(have) == 0 && next >= end && !more;
             if (all_done || qn > (uint32_t)(kCountSlotCap - 64 * kCountLaneCap) ||
                 nr > (uint32_t)(kCountRunCap - 256) || n_blocked > 16) {
@@ -1638,6 +1688,7 @@ constexpr uint32_t kPersistentBlocks = EMT_PERSISTENT_BLOCKS;  // 8 blocks of 4 
 // the counting kernel's grid: one resident generation (4 workgroups per CU,
 // bound by its LDS and registers), so no workgroup waits for another's slot
 constexpr uint32_t kCountBlocks = EMT_COUNT_BLOCKS;
+static_assert(kCountBlocks % 8 == 0, "whole workgroups per XCD");
 
 }  // namespace
 
@@ -1646,7 +1697,7 @@ size_t scan_scratch_words(uint32_t n_cap) { return (size_t)n_cap / kScanTile + 2
 void launch_prepare(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {
     k_zero<<<blocks_for(c.n_cells, 1024), kBlock, 0, s>>>(d.cnt, d.view_seeds, d.view_cand,
                                                           d.view_ntr, d.view_cursor, d.cell_count,
-                                                          d.desc);
+                                                          d.grab, d.desc);
 }
 
 void launch_bin(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
