@@ -436,8 +436,10 @@ struct Pencil {
         const float e1 = fmaf((float)ien, ues, ue0), e2 = e1 + uew;
         const float tan_ = fmaxf(tlo, fminf(e1, e2)), tbn = fminf(thi, fmaxf(e1, e2));
         const float fa = fmaf(tan_, df, gf), fb = fmaf(tbn, df, gf);
-        const int jf0n = max(0, (int)floorf(fmaxf((fminf(fa, fb) - rr) * icf, -1.0f)));
-        const int jf1n = min(nf - 1, (int)floorf(fminf((fmaxf(fa, fb) + rr) * icf, (float)nf)));
+        // truncation is the floor for the lower bound (clamped at 0); for
+        // the upper one it can only add a cell, which costs tests, not results
+        const int jf0n = (int)fmaxf((fminf(fa, fb) - rr) * icf, 0.0f);
+        const int jf1n = min(nf - 1, (int)fmaxf(fminf((fmaxf(fa, fb) + rr) * icf, (float)nf), -1.0f));
         if (step_e) {
             ie = ien;
             ta = tan_;
@@ -450,14 +452,18 @@ struct Pencil {
         const float f1 = fmaf((float)j, ufs, uf0), f2 = f1 + ufw;
         const float tc = fmaxf(ta, fminf(f1, f2)), td = fminf(tb, fmaxf(f1, f2));
         const float xa = fmaf(tc, dx, gx), xb = fmaf(td, dx, gx);
-        const int x0 = max(0, (int)floorf(fmaxf((fminf(xa, xb) - rr) * icx, -1.0f)));
-        const int x1 = min(nx - 1, (int)floorf(fminf((fmaxf(xa, xb) + rr) * icx, (float)nx)));
+        const int x0 = (int)fmaxf((fminf(xa, xb) - rr) * icx, 0.0f);
+        const int x1 = min(nx - 1, (int)fmaxf(fminf((fmaxf(xa, xb) + rr) * icx, (float)nx), -1.0f));
         const bool ok = live && j <= jf1 && tc <= td && x0 <= x1;
         jf = j + 1;
         const int iy = e_is_y ? ie : j, iz = e_is_y ? j : ie;
         const uint32_t row = off + (uint32_t)((iz * ny + iy) * nx);
-        out.k = ok ? cs[row + x0] : 0u;
-        out.e = ok ? cs[row + x1 + 1] : 0u;
+        // 32-bit byte offsets from the table base (the table is far below
+        // 4 GB), so the loads take a scalar base and one vector offset
+        const char *base = reinterpret_cast<const char *>(cs);
+        const uint32_t b0 = (row + (uint32_t)x0) * 4u, b1 = (row + (uint32_t)x1 + 1u) * 4u;
+        out.k = ok ? *reinterpret_cast<const uint32_t *>(base + b0) : 0u;
+        out.e = ok ? *reinterpret_cast<const uint32_t *>(base + b1) : 0u;
     }
 };
 
@@ -1439,6 +1445,7 @@ __global__ void __launch_bounds__(kBlock) k_rank(DevPtrs d, const unsigned long 
         const uint32_t b = d.view_tr_off[v], e = b + d.view_ntr[v];
         const unsigned long long key = gkey[s];
         uint32_t rank = 0;
+#pragma unroll 8
         for (uint32_t t = b; t < e; ++t) rank += gkey[t] < key ? 1u : 0u;
         d.track_cand[b + rank] = ci;
         d.tg_n[b + rank] = d.mcount[ci];
@@ -1522,21 +1529,32 @@ __global__ void __launch_bounds__(kBlock) k_fit(DevPtrs d, Params P) {
         for (int u = 0; u < 3; ++u) s1[u] = wave_sum(s1[u]);
         for (int u = 0; u < 6; ++u) s2[u] = wave_sum(s2[u]);
 
-        // 3. grain order by (t, input index), rank by counting
-        for (uint32_t q = lane; q < m; q += 64) {
-            const long long tq = d.tvals[base + q];
-            const uint32_t kq = d.tord[base + q];
-            const int oq = d.sg[kq].w;
+        // 3. grain order by (t, input index), rank by counting: the wave
+        // loads 64 entries at a time into registers and every lane compares
+        // its own entry with each of them through readlane (input indices
+        // are distinct, so no entry outranks itself)
+        for (uint32_t q0 = 0; q0 < m; q0 += 64) {
+            const uint32_t q = q0 + (uint32_t)lane;
+            const bool vq = q < m;
+            const long long tq = vq ? d.tvals[base + q] : 0;
+            const int oq = vq ? d.sg[d.tord[base + q]].w : 0;
             uint32_t rank = 0;
-            for (uint32_t o = 0; o < m; ++o) {
-                const long long to = d.tvals[base + o];
-                if (to < tq) {
-                    ++rank;
-                } else if (to == tq && o != q) {
-                    rank += d.sg[d.tord[base + o]].w < oq ? 1u : 0u;
+            for (uint32_t o0 = 0; o0 < m; o0 += 64) {
+                const uint32_t o = o0 + (uint32_t)lane;
+                const long long tl = o < m ? d.tvals[base + o] : 0;
+                const int ol = o < m ? d.sg[d.tord[base + o]].w : 0;
+                const int t_lo = (int)(uint32_t)(unsigned long long)tl;
+                const int t_hi = (int)(uint32_t)((unsigned long long)tl >> 32);
+                const uint32_t cnt = min(64u, m - o0);
+                for (uint32_t i = 0; i < cnt; ++i) {
+                    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(t_lo, (int)i);
+                    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(t_hi, (int)i);
+                    const long long to = (long long)(((unsigned long long)hi << 32) | lo);
+                    const int oo = __builtin_amdgcn_readlane(ol, (int)i);
+                    rank += (to < tq || (to == tq && oo < oq)) ? 1u : 0u;
                 }
             }
-            d.out_grains[base + rank] = (uint32_t)oq;
+            if (vq) d.out_grains[base + rank] = (uint32_t)oq;
         }
 
         // 4. fit (every lane computes the same values)
