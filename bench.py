@@ -123,7 +123,7 @@ def measure_batch(emt, torch, views, calls: int, warmup: int) -> dict:
 
 def measure_served(emt, views, n_req: int, warmup: int, batch: int = 16,
                    fracs=(0.5, 0.9), seed: int = 0x5E4FE, n_pipes: int = 2,
-                   max_batch: int = 64) -> dict:
+                   max_batch: int = 16) -> dict:
     """The served form on a pool of c4 views (host arrays, as a microscope
     hands them over). First the batched capacity mu_b (views/s through
     emt_track_views, batch views per call) and the plain one-view-per-call
@@ -312,7 +312,7 @@ def main() -> int:
             forms["served_c4"] = measure_served(emt, vs, args.served_requests, args.served_warmup)
             forms["served_c4"]["workload"] = (
                 "c4: Poisson stream drawn from 96 views of 100^2, 200^2 or 350^2 x 50 um, "
-                "fog 1-10/1000 um^3, 2449 tracks/mm^2; two pipelines, up to 64 views a batch")
+                "fog 1-10/1000 um^3, 2449 tracks/mm^2; two pipelines, up to 16 views a batch")
     if forms:
         out["forms"] = forms
     if not args.no_cpu_baseline:

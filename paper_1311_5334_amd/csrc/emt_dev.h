@@ -42,7 +42,8 @@ struct BatchDesc {
 
 // Cell edges by grain density: bucket b holds views with at least
 // kCellEdge0 * 2^(b-1) grains per 1000 um^3 (b = 0: below kCellEdge0).
-constexpr int kGrabWords = 8 * 16;  // one counter per XCD, 64 B apart
+// Per-XCD seed-range counters of the counting kernel, 64 B apart.
+constexpr int kGrabWords = 8 * 16;
 constexpr int kCellBuckets = 8;
 constexpr double kCellEdge0 = 0.75;
 

@@ -19,6 +19,22 @@ namespace emt {
 
 namespace {
 
+// Tuning constants; -D on the compiler line overrides them.
+#ifndef EMT_DYN_MIN_SEEDS
+#define EMT_DYN_MIN_SEEDS 8000000
+#endif
+#ifndef EMT_COUNT_SLOT_CAP
+#define EMT_COUNT_SLOT_CAP 4096
+#endif
+#ifndef EMT_COUNT_RUN_CAP
+#define EMT_COUNT_RUN_CAP 512
+#endif
+#ifndef EMT_COUNT_LANE_CAP
+#define EMT_COUNT_LANE_CAP 32
+#endif
+#ifndef EMT_CHUNK_SEEDS
+#define EMT_CHUNK_SEEDS 64
+#endif
 constexpr float kMargin = 4.0f;  // units added to every cell window
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;
@@ -503,6 +519,36 @@ __device__ __forceinline__ bool cyl_hit(int4 h, int4 A, int4 B, int tol_r) {
     return cc <= (long long)tol_r * tol_r * D;
 }
 
+// Next grab of items for the calling wave: its own
+// XCD's range first, then the others. grab[16 x] is range x's offset
+// counter. Grabs are a quarter of a range's remainder per wave of the XCD,
+// within [gmin, gmax] and a multiple of gmin. Returns false when every
+// range is used up. Wave-uniform.
+__device__ __forceinline__ bool xcd_grab(uint32_t *grab, uint32_t xcd, uint32_t per,
+                                         uint32_t n_items, uint32_t wpx, uint32_t gmin,
+                                         uint32_t gmax, uint32_t &next, uint32_t &end) {
+    uint32_t s = 0xffffffffu, e = 0;
+    if (lane_id() == 0) {
+        for (uint32_t t = 0; t < 8; ++t) {
+            const uint32_t x = (xcd + t) & 7u;
+            const uint32_t lo = min(n_items, x * per), hi = min(n_items, x * per + per);
+            uint32_t *ctr = grab + 16 * x;
+            const uint32_t cur = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (cur >= hi - lo) continue;
+            uint32_t g = (hi - lo - cur) / (4u * wpx);
+            g = min(gmax, max(gmin, (g + gmin - 1u) / gmin * gmin));
+            const uint32_t at = atomicAdd(ctr, g);
+            if (at >= hi - lo) continue;
+            s = lo + at;
+            e = min(hi, s + g);
+            break;
+        }
+    }
+    next = (uint32_t)__shfl((int)s, 0);
+    end = (uint32_t)__shfl((int)e, 0);
+    return next != 0xffffffffu;
+}
+
 // ----------------------------------------------------------------- seeds
 //
 // One wave per anchor grain p; lanes take the (y, z) rows of the cell box
@@ -831,21 +877,6 @@ __global__ void __launch_bounds__(kBlock) k_lines(DevPtrs d, Caps c, Params P) {
 // time is the sum of its lines' work rather than a multiple of the longest
 // one. Hit counts of a closed slot are final after the next queue flush,
 // which writes them out and frees the slot.
-#ifndef EMT_COUNT_SLOT_CAP
-#define EMT_COUNT_SLOT_CAP 4096
-#endif
-#ifndef EMT_COUNT_RUN_CAP
-#define EMT_COUNT_RUN_CAP 512
-#endif
-#ifndef EMT_COUNT_LANE_CAP
-#define EMT_COUNT_LANE_CAP 32
-#endif
-#ifndef EMT_DYN_MIN_SEEDS
-#define EMT_DYN_MIN_SEEDS 8000000
-#endif
-#ifndef EMT_CHUNK_SEEDS
-#define EMT_CHUNK_SEEDS 64
-#endif
 constexpr int kCountSlots = 128;
 constexpr int kCountSlotCap = EMT_COUNT_SLOT_CAP;  // queued tests per wave
 constexpr int kCountRunCap = EMT_COUNT_RUN_CAP;    // queued runs per wave
@@ -893,34 +924,6 @@ __device__ __forceinline__ void count_flush(CountLds &Q, uint32_t qn, int tol_r,
     wave_lds_sync();
 }
 
-// Next grab of seeds for the calling wave: its own XCD's range first, then
-// the others. grab[16 x] is range x's offset counter. Returns false when
-// every range is used up. Wave-uniform.
-__device__ __forceinline__ bool count_grab(uint32_t *grab, uint32_t xcd, uint32_t per,
-                                           uint32_t n_items, uint32_t wpx, uint32_t &next,
-                                           uint32_t &end) {
-    uint32_t s = 0xffffffffu, e = 0;
-    if (lane_id() == 0) {
-        for (uint32_t t = 0; t < 8; ++t) {
-            const uint32_t x = (xcd + t) & 7u;
-            const uint32_t lo = min(n_items, x * per), hi = min(n_items, x * per + per);
-            uint32_t *ctr = grab + 16 * x;
-            const uint32_t cur = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (cur >= hi - lo) continue;
-            uint32_t g = (hi - lo - cur) / (4u * wpx);
-            g = min(4096u, max(64u, (g + 63u) & ~63u));
-            const uint32_t at = atomicAdd(ctr, g);
-            if (at >= hi - lo) continue;
-            s = lo + at;
-            e = min(hi, s + g);
-            break;
-        }
-    }
-    next = (uint32_t)__shfl((int)s, 0);
-    end = (uint32_t)__shfl((int)e, 0);
-    return next != 0xffffffffu;
-}
-
 __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
     __shared__ CountLds sQ[kWaves];
     const int lane = lane_id();
@@ -942,7 +945,7 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
     const uint32_t gw = grid_tid() >> 6, nwv = grid_threads() >> 6;
     const uint32_t xcd = blockIdx.x & 7u;
     const uint32_t per = ((n_items + 7u) / 8u + 63u) & ~63u;
-    const uint32_t wpx = (gridDim.x >> 3) * kWaves;
+    const uint32_t wpx = max(1u, (gridDim.x >> 3) * kWaves);
     uint32_t chunk = gw * kChunkSeeds;
     uint32_t next = dyn ? 0u : min(chunk, n_items);
     uint32_t end = dyn ? 0u : min(n_items, chunk + kChunkSeeds);
@@ -958,7 +961,8 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
     for (;;) {
         {
             if (dyn) {
-                if (next >= end && more) more = count_grab(d.grab, xcd, per, n_items, wpx, next, end);
+                if (next >= end && more)
+                    more = xcd_grab(d.grab, xcd, per, n_items, wpx, 64u, 4096u, next, end);
             } else {
                 more = chunk + nwv * kChunkSeeds < n_items;
                 if (next >= end && more) {
