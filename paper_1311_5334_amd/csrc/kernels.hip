@@ -32,6 +32,9 @@ namespace {
 #ifndef EMT_COUNT_LANE_CAP
 #define EMT_COUNT_LANE_CAP 32
 #endif
+#ifndef EMT_COUNT_FETCH
+#define EMT_COUNT_FETCH 8
+#endif
 #ifndef EMT_CHUNK_SEEDS
 #define EMT_CHUNK_SEEDS 64
 #endif
@@ -883,7 +886,9 @@ constexpr int kCountRunCap = EMT_COUNT_RUN_CAP;    // queued runs per wave
 constexpr int kCountLaneCap = EMT_COUNT_LANE_CAP;  // tests a lane queues per step
 constexpr int kCountMaskWords = kCountSlotCap / 64;
 constexpr int kChunkSeeds = EMT_CHUNK_SEEDS;
-static_assert(kCountSlotCap > 64 * kCountLaneCap, "a step must fit the slot queue");
+constexpr int kFetch = EMT_COUNT_FETCH;  // pencils a lane fetches per step
+static_assert(64 * kFetch <= kCountRunCap, "a step's runs must fit the run queue");
+static_assert(kCountSlotCap >= 64 * kCountLaneCap, "a step's tests must fit the slot queue");
 static_assert(kCountMaskWords <= 64, "one mask word per lane");
 
 struct CountLds {
@@ -892,8 +897,7 @@ struct CountLds {
     uint32_t cnt[kCountSlots];
     unsigned long long mask[kCountMaskWords];
     uint32_t before[kCountMaskWords];
-    uint32_t run_k[kCountRunCap];
-    uint32_t run_tag[kCountRunCap];  // first queue slot | seed slot << 16
+    uint2 run[kCountRunCap];  // first grain, first queue slot | seed slot << 16
 };
 
 __device__ __forceinline__ void count_flush(CountLds &Q, uint32_t qn, int tol_r, const int4 *__restrict__ sg,
@@ -912,8 +916,9 @@ __device__ __forceinline__ void count_flush(CountLds &Q, uint32_t qn, int tol_r,
         const unsigned long long word = Q.mask[w];
         if (s < qn) {
             const uint32_t r = Q.before[w] + (uint32_t)__popcll(word & upto) - 1u;
-            const uint32_t tag = Q.run_tag[r];
-            const uint32_t kk = Q.run_k[r] + (s - (tag & 0xffffu));
+            const uint2 rec = Q.run[r];
+            const uint32_t tag = rec.y;
+            const uint32_t kk = rec.x + (s - (tag & 0xffffu));
             const uint32_t sl = tag >> 16;
             const int4 h = sg[kk];
             if (cyl_hit(h, Q.pa[sl], Q.pb[sl], tol_r)) atomicAdd(&Q.cnt[sl], 1u);
@@ -956,8 +961,26 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
     int cur = lane;
     Pencil W;
     W.live = false;
-    Run s0 = {0, 0}, s1 = {0, 0}, s2 = {0, 0}, s3 = {0, 0};
+    Run run[kFetch];
+#pragma unroll
+    for (int f = 0; f < kFetch; ++f) run[f] = Run{0, 0};
     uint32_t qn = 0, nr = 0;
+    // counts of closed slots are final after a flush: write them, free slots
+    auto finalize = [&]() {
+        if (pend0) {
+            const uint32_t n = Q.cnt[lane];
+            hits += n;
+            d.seed_n[idx0] = n >= (uint32_t)P.n_min ? n : 0u;
+            pend0 = false;
+        }
+        if (pend1) {
+            const uint32_t n = Q.cnt[lane + 64];
+            hits += n;
+            d.seed_n[idx1] = n >= (uint32_t)P.n_min ? n : 0u;
+            pend1 = false;
+        }
+        wave_lds_sync();
+    };
     for (;;) {
         {
             if (dyn) {
@@ -994,91 +1017,69 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
                 have = true;
             }
             next = min(end, next + (uint32_t)__popcll(wm));
-            // fetch four runs once the previous four are queued
-            if (have && W.live && s0.k >= s0.e && s1.k >= s1.e && s2.k >= s2.e && s3.k >= s3.e) {
-                W.fetch(d.cell_start, s0);
-                W.fetch(d.cell_start, s1);
-                W.fetch(d.cell_start, s2);
-                W.fetch(d.cell_start, s3);
+            // fetch kFetch runs once the previous ones are queued
+            bool drained = true;
+#pragma unroll
+            for (int f = 0; f < kFetch; ++f) drained = drained && run[f].k >= run[f].e;
+            if (have && W.live && drained) {
+#pragma unroll
+                for (int f = 0; f < kFetch; ++f) W.fetch(d.cell_start, run[f]);
             }
-            uint32_t budget = kCountLaneCap;
-            const uint32_t l0 = min(s0.e > s0.k ? s0.e - s0.k : 0u, budget);
-            budget -= l0;
-            const uint32_t l1 = min(s1.e > s1.k ? s1.e - s1.k : 0u, budget);
-            budget -= l1;
-            const uint32_t l2 = min(s2.e > s2.k ? s2.e - s2.k : 0u, budget);
-            budget -= l2;
-            const uint32_t l3 = min(s3.e > s3.k ? s3.e - s3.k : 0u, budget);
-            const uint32_t nrun = (l0 > 0) + (l1 > 0) + (l2 > 0) + (l3 > 0);
-            const uint32_t mine = l0 + l1 + l2 + l3;
+            // queue up to kCountLaneCap grains of the lane's runs
+            uint32_t budget = kCountLaneCap, mine = 0, nrun = 0;
+            uint32_t len[kFetch];
+#pragma unroll
+            for (int f = 0; f < kFetch; ++f) {
+                len[f] = min(run[f].e > run[f].k ? run[f].e - run[f].k : 0u, budget);
+                budget -= len[f];
+                mine += len[f];
+                nrun += len[f] ? 1u : 0u;
+            }
             const uint32_t pk = mine | (nrun << 16);
             const uint32_t incl = wave_incl_scan_dpp(pk);
             const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-            const uint32_t ex = incl - pk;
+            // room first: test what is queued if this step's runs do not fit
+            if (qn + (tot & 0xffffu) > (uint32_t)kCountSlotCap ||
+                nr + (tot >> 16) > (uint32_t)kCountRunCap) {
+                count_flush(Q, qn, P.r, d.sg, lane);
+                qn = 0;
+                nr = 0;
+                finalize();
+            }
             if (mine) {
+                const uint32_t ex = incl - pk;
                 uint32_t pos = qn + (ex & 0xffffu);
                 uint32_t ri = nr + (ex >> 16);
                 const uint32_t tag = (uint32_t)cur << 16;
-                if (l0) {
-                    Q.run_k[ri] = s0.k;
-                    Q.run_tag[ri++] = pos | tag;
-                    atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
-                    pos += l0;
-                    s0.k += l0;
-                }
-                if (l1) {
-                    Q.run_k[ri] = s1.k;
-                    Q.run_tag[ri++] = pos | tag;
-                    atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
-                    pos += l1;
-                    s1.k += l1;
-                }
-                if (l2) {
-                    Q.run_k[ri] = s2.k;
-                    Q.run_tag[ri++] = pos | tag;
-                    atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
-                    pos += l2;
-                    s2.k += l2;
-                }
-                if (l3) {
-                    Q.run_k[ri] = s3.k;
-                    Q.run_tag[ri] = pos | tag;
-                    atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
-                    s3.k += l3;
+#pragma unroll
+                for (int f = 0; f < kFetch; ++f) {
+                    if (len[f]) {
+                        Q.run[ri++] = make_uint2(run[f].k, pos | tag);
+                        atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
+                        pos += len[f];
+                        run[f].k += len[f];
+                    }
                 }
             }
             qn += tot & 0xffffu;
             nr += tot >> 16;
             tests += mine;
             // a seed whose walk ended and whose runs are all queued is closed
-            if (have && !W.live && s0.k >= s0.e && s1.k >= s1.e && s2.k >= s2.e &&
-                s3.k >= s3.e) {
+            bool queued = true;
+#pragma unroll
+            for (int f = 0; f < kFetch; ++f) queued = queued && run[f].k >= run[f].e;
+            if (have && !W.live && queued) {
                 have = false;
                 if (cur == lane) pend0 = true; else pend1 = true;
             }
             const bool blocked = !have && pend0 && pend1;
             const uint32_t n_blocked = (uint32_t)__popcll(__ballot(blocked));
-
             const bool all_done = __ballot(have) == 0 && next >= end && !more;
-            if (all_done || qn > (uint32_t)(kCountSlotCap - 64 * kCountLaneCap) ||
-                nr > (uint32_t)(kCountRunCap - 256) || n_blocked > 16) {
+            if (all_done || n_blocked > 16) {
                 if (qn) count_flush(Q, qn, P.r, d.sg, lane);
                 qn = 0;
                 nr = 0;
-                // every closed slot is final now
-                if (pend0) {
-                    const uint32_t n = Q.cnt[lane];
-                    hits += n;
-                    d.seed_n[idx0] = n >= (uint32_t)P.n_min ? n : 0u;
-                    pend0 = false;
-                }
-                if (pend1) {
-                    const uint32_t n = Q.cnt[lane + 64];
-                    hits += n;
-                    d.seed_n[idx1] = n >= (uint32_t)P.n_min ? n : 0u;
-                    pend1 = false;
-                }
-                wave_lds_sync();
+                finalize();
                 if (all_done) break;
             }
         }
