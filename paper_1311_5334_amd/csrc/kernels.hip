@@ -30,13 +30,13 @@ namespace {
 #define EMT_COUNT_RUN_CAP 512
 #endif
 #ifndef EMT_COUNT_LANE_CAP
-#define EMT_COUNT_LANE_CAP 32
+#define EMT_COUNT_LANE_CAP 64
 #endif
 #ifndef EMT_COUNT_FETCH
 #define EMT_COUNT_FETCH 8
 #endif
 #ifndef EMT_CHUNK_SEEDS
-#define EMT_CHUNK_SEEDS 64
+#define EMT_CHUNK_SEEDS 128
 #endif
 constexpr float kMargin = 4.0f;  // units added to every cell window
 constexpr int kScanItems = 8;
