@@ -59,6 +59,9 @@ struct emt_ctx {
     unsigned long long cap_seeds = 0;
     // capacities learned from earlier calls
     double seeds_per_grain = 256.0, cand_per_grain = 8.0, mem_per_cand = 24.0;
+    // grid-wide merge rounds for the next call: two more than the last call
+    // needed in all (the single-workgroup tail finishes any rest)
+    int next_wide = 0;
 
     // pinned host buffers
     int32_t *h_xyz = nullptr;
@@ -430,7 +433,8 @@ void launch_stages(emt_ctx *ctx, const Caps &c, hipStream_t s, int stage) {
 bool same_caps(const Caps &a, const Caps &b) {
     return a.n_total == b.n_total && a.n_views == b.n_views && a.n_cells == b.n_cells &&
            a.max_view_n == b.max_view_n && a.seed_cap == b.seed_cap &&
-           a.cand_cap == b.cand_cap && a.mem_cap == b.mem_cap;
+           a.cand_cap == b.cand_cap && a.mem_cap == b.mem_cap &&
+           a.wide_rounds == b.wide_rounds;
 }
 
 void drop_graphs(emt_ctx *ctx) {
@@ -578,6 +582,7 @@ int batch_caps(const emt_ctx *ctx, unsigned long long n_total, uint32_t n_views,
                          4096, (unsigned long long)(ctx->seeds_per_grain * (double)c.n_total)));
     c.cand_cap = clamp_u32(ctx->cand_per_grain * (double)c.n_total);
     c.mem_cap = clamp_u32(ctx->mem_per_cand * (double)c.cand_cap);
+    c.wide_rounds = ctx->next_wide > 0 ? ctx->next_wide : max_wide_rounds();
     *out = c;
     return EMT_OK;
 }
@@ -635,14 +640,13 @@ int emt_create(const emt_config *cfg, emt_ctx **out) {
     ctx->P.R = cfg->seed_dist;
     ctx->P.r = cfg->tol_radius;
     ctx->P.n_min = cfg->min_grains;
-    ctx->P.count_lanes = 1;
     // cell edges: per view from the tuned density table when none is given
     ctx->P.auto_cells = (cfg->cell[0] || cfg->cell[1] || cfg->cell[2]) ? 0 : 1;
     for (int m = 0; m < 3; ++m) ctx->P.cell_req[m] = cfg->cell[m] ? cfg->cell[m] : kDefaultCell[m];
     for (int b = 0; b < kCellBuckets; ++b)
         for (int m = 0; m < 3; ++m) ctx->P.cell_tab[b][m] = kTunedCells[b][m];
     ctx->P.flags = cfg->flags;
-    // Tuning hooks: cell edges "x,y,z" in units, and lanes per seed line.
+    // Tuning hook: fixed cell edges "x,y,z" in units.
     if (const char *e = std::getenv("EMT_CELL")) {
         int v[3];
         if (std::sscanf(e, "%d,%d,%d", &v[0], &v[1], &v[2]) == 3 && v[0] > 0 && v[1] > 0 &&
@@ -650,10 +654,6 @@ int emt_create(const emt_config *cfg, emt_ctx **out) {
             for (int m = 0; m < 3; ++m) ctx->P.cell_req[m] = v[m];
             ctx->P.auto_cells = 0;
         }
-    }
-    if (const char *e = std::getenv("EMT_COUNT_LANES")) {
-        const int k = std::atoi(e);
-        ctx->P.count_lanes = (k >= 4) ? 4 : (k >= 2 ? 2 : 1);
     }
     if (const char *e = std::getenv("EMT_NO_GRAPH")) ctx->use_graphs = (std::atoi(e) == 0);
     // Test hook: start from tiny capacities so the first call overflows and
@@ -838,6 +838,7 @@ int finish_views(emt_ctx *ctx, emt_view_out *out) {
         o.stats.n_candidates = ctx->h.view_cand[v];
         o.stats.n_tracks = nt;
     }
+    ctx->next_wide = std::max(6, std::min(max_wide_rounds(), (int)h.rounds + 2));
     emt_call_stats &st = ctx->last;
     st = emt_call_stats{};
     st.n_seeds = h.n_seeds;

@@ -48,7 +48,7 @@ constexpr int kCellBuckets = 8;
 constexpr double kCellEdge0 = 0.75;
 
 struct Params {
-    int32_t R, r, n_min, count_lanes;
+    int32_t R, r, n_min, pad0;
     int32_t cell_req[3];  // fixed cell edges, used when auto_cells == 0
     uint32_t flags;
     int32_t auto_cells;   // 1: per view from cell_tab by density
@@ -64,7 +64,7 @@ struct Counters {
     unsigned long long hits;
     uint32_t n_cand;
     uint32_t n_members;
-    uint32_t n_act[2];
+    uint32_t n_act[2];  // [0]: candidates taking part in the merge
     uint32_t n_acc;
     uint32_t n_track_grains;
     uint32_t rounds;
@@ -161,6 +161,8 @@ struct Caps {
     unsigned long long seed_cap;
     uint32_t cand_cap;
     uint32_t mem_cap;
+    int32_t wide_rounds;      // grid-wide merge rounds before the tail kernel
+    int32_t pad;
 };
 
 // Launchers (kernels.hip). All run on `s` and only enqueue work.
@@ -177,5 +179,6 @@ void launch_copy_out(const DevPtrs &d, const Caps &c, const Params &P, hipStream
 
 size_t scan_scratch_words(uint32_t n_cap);
 int max_merge_rounds();
+int max_wide_rounds();
 
 }  // namespace emt

@@ -35,6 +35,15 @@ namespace {
 #ifndef EMT_COUNT_FETCH
 #define EMT_COUNT_FETCH 8
 #endif
+#ifndef EMT_MEMBER_LANES
+#define EMT_MEMBER_LANES 4
+#endif
+#ifndef EMT_MEMBER_LANE_CAP
+#define EMT_MEMBER_LANE_CAP 32
+#endif
+#ifndef EMT_MEMBER_SLOT_CAP
+#define EMT_MEMBER_SLOT_CAP 4096
+#endif
 #ifndef EMT_CHUNK_SEEDS
 #define EMT_CHUNK_SEEDS 128
 #endif
@@ -626,11 +635,6 @@ __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
     }
 }
 
-__global__ void k_seed_total(DevPtrs d, Caps c) {
-    if (grid_tid() != 0) return;
-    // the scan total counts every seed; it wraps only above 2^32 - 1 per call
-    d.cnt->n_seeds = d.seed_off[d.desc->n_total];
-}
 
 // ------------------------------------------------------- count / members
 //
@@ -644,9 +648,10 @@ __global__ void k_seed_total(DevPtrs d, Caps c) {
 // counted with LDS atomics. Only the cheap walk is divergent across lanes;
 // the predicate work is dense.
 
-constexpr int kSlotCap = 2048;            // queued grain tests per wave
-constexpr int kRunCap = 768;              // queued runs per wave
-constexpr int kLaneCap = 16;              // grains one lane may queue per step
+constexpr int kSlotCap = EMT_MEMBER_SLOT_CAP;  // queued grain tests per wave
+constexpr int kRunCap = 768;                   // queued runs per wave
+constexpr int kLaneCap = EMT_MEMBER_LANE_CAP;  // grains one lane may queue per step
+static_assert(kSlotCap >= 2 * 64 * kLaneCap && kSlotCap <= 4096, "member queue size");
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaskWords = kSlotCap / 64;
 
@@ -692,7 +697,6 @@ __device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t x) {
     return v;
 }
 
-template <bool kMembers>
 __device__ __forceinline__ void flush_queue(QueueLds &Q, uint32_t qn, int tol_r, const int4 *__restrict__ sg,
                                             uint32_t *__restrict__ members, int lane) {
     wave_lds_sync();
@@ -716,7 +720,7 @@ __device__ __forceinline__ void flush_queue(QueueLds &Q, uint32_t qn, int tol_r,
             const int4 h = sg[kk];
             if (cyl_hit(h, Q.pa[sl], Q.pb[sl], tol_r)) {
                 const uint32_t pos = atomicAdd(&Q.cnt[sl], 1u);
-                if (kMembers && pos < Q.ncap[sl]) members[Q.out_off[sl] + pos] = kk;
+                if (pos < Q.ncap[sl]) members[Q.out_off[sl] + pos] = kk;
             }
         }
     }
@@ -725,43 +729,29 @@ __device__ __forceinline__ void flush_queue(QueueLds &Q, uint32_t qn, int tol_r,
     wave_lds_sync();
 }
 
-template <bool kMembers, int kPer>
-__global__ void __launch_bounds__(kBlock) k_lines(DevPtrs d, Caps c, Params P) {
+template <int kPer>
+__global__ void __launch_bounds__(kBlock) k_members(DevPtrs d, Caps c, Params P) {
     __shared__ QueueLds sQ[kWaves];
     const int lane = lane_id();
     const int slot = lane / kPer, sub = lane % kPer;
     constexpr int kItems = 64 / kPer;
     QueueLds &Q = sQ[threadIdx.x >> 6];
-    unsigned long long n_items;
-    if (kMembers) {
-        const uint32_t nc = d.cnt->n_cand;
-        n_items = d.cnt->err ? 0ull : (nc < c.cand_cap ? nc : c.cand_cap);
-    } else {
-        const unsigned long long ns = d.cnt->n_seeds;
-        n_items = ns < c.seed_cap ? ns : c.seed_cap;
-    }
+    const uint32_t nc = d.cnt->n_cand;
+    const unsigned long long n_items = d.cnt->err ? 0ull : (nc < c.cand_cap ? nc : c.cand_cap);
     if (lane < kMaskWords) Q.mask[lane] = 0ull;
     wave_lds_sync();
     const unsigned long long gw = grid_tid() >> 6, nw = grid_threads() >> 6;
-    unsigned long long tests = 0, hits = 0;
     for (unsigned long long base = gw * kItems; base < n_items; base += nw * kItems) {
         const unsigned long long idx = base + (unsigned long long)slot;
         const bool valid = idx < n_items;
         uint32_t p = 0, q = 0, v = 0, ncap = 0, off = 0;
         if (valid) {
-            if (kMembers) {
-                const Cand cd = d.cand[idx];
-                p = cd.p;
-                q = cd.q;
-                v = cd.v;
-                off = d.mem_off[idx];
-                ncap = ((unsigned long long)off + cd.n <= c.mem_cap) ? cd.n : 0u;
-            } else {
-                const uint2 pq = d.seeds[idx];
-                p = pq.x;
-                q = pq.y;
-                v = d.view_of[p];
-            }
+            const Cand cd = d.cand[idx];
+            p = cd.p;
+            q = cd.q;
+            v = cd.v;
+            off = d.mem_off[idx];
+            ncap = ((unsigned long long)off + cd.n <= c.mem_cap) ? cd.n : 0u;
         }
         const int4 gi = d.sg[p], gj = d.sg[q];
         const int dx = gj.x - gi.x, dy = gj.y - gi.y, dz = gj.z - gi.z;
@@ -776,7 +766,7 @@ __global__ void __launch_bounds__(kBlock) k_lines(DevPtrs d, Caps c, Params P) {
         }
         wave_lds_sync();
         Pencil W;
-        W.init(&d.grids[v], gi, dx, dy, dz, P.r, valid && (!kMembers || ncap > 0), sub, kPer);
+        W.init(&d.grids[v], gi, dx, dy, dz, P.r, valid && ncap > 0, sub, kPer);
         Run s0 = {0, 0}, s1 = {0, 0}, s2 = {0, 0}, s3 = {0, 0};
         uint32_t qn = 0, nr = 0;
         for (;;) {
@@ -836,41 +826,22 @@ __global__ void __launch_bounds__(kBlock) k_lines(DevPtrs d, Caps c, Params P) {
             }
             qn += tot & 0xffffu;
             nr += tot >> 16;
-            tests += mine;
             if (qn > (uint32_t)(kSlotCap - 64 * kLaneCap) || nr > (uint32_t)(kRunCap - 256)) {
-                flush_queue<kMembers>(Q, qn, P.r, d.sg, d.members, lane);
+                flush_queue(Q, qn, P.r, d.sg, d.members, lane);
                 qn = 0;
                 nr = 0;
             }
         }
-        if (qn) flush_queue<kMembers>(Q, qn, P.r, d.sg, d.members, lane);
+        if (qn) flush_queue(Q, qn, P.r, d.sg, d.members, lane);
         wave_lds_sync();
         const uint32_t n = Q.cnt[slot];
-        if (sub != 0) {
-            // one lane per item reports
-        } else if (kMembers) {
-            if (valid && ncap > 0 && n != ncap) {
-                // the same walk and predicate as the count: never expected;
-                // keep every entry a valid grain index and flag an internal error
-                for (uint32_t t = n; t < ncap; ++t) d.members[off + t] = p;
-                atomicOr(&d.cnt->err, 2u);
-            }
-        } else {
-            hits += valid ? n : 0u;
-            const bool pred = valid && n >= (uint32_t)P.n_min;
-            // a seed's count is kept only if it passes; a scan over these
-            // compacts the candidates in seed order
-            if (valid) d.seed_n[idx] = pred ? n : 0u;
+        if (sub == 0 && valid && ncap > 0 && n != ncap) {
+            // the same walk and predicate as the count: never expected;
+            // keep every entry a valid grain index and flag an internal error
+            for (uint32_t t = n; t < ncap; ++t) d.members[off + t] = p;
+            atomicOr(&d.cnt->err, 2u);
         }
         wave_lds_sync();
-    }
-    if (!kMembers) {
-        tests = wave_sum(tests);
-        hits = wave_sum(hits);
-        if (lane == 0) {
-            atomicAdd(&d.cnt->tests, tests);
-            atomicAdd(&d.cnt->hits, hits);
-        }
     }
 }
 
@@ -1092,9 +1063,18 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
     }
 }
 
-// Candidates in seed order: position from the flag scan of seed_n.
+// Candidates in seed order: position from the flag scan of seed_n; their
+// counts (for the member offsets); and the seeds and candidates of each
+// view, from the offsets (views are contiguous in anchor order, so in seed
+// and in candidate order too).
 __global__ void __launch_bounds__(kBlock) k_cand_scatter(DevPtrs d, Caps c) {
     const uint32_t ns = min(d.cnt->n_seeds, (uint32_t)c.seed_cap);
+    for (uint32_t v = grid_tid(); v < d.desc->n_views; v += grid_threads()) {
+        const uint32_t g0 = d.grids[v].grain_off, g1 = g0 + d.grids[v].n;
+        const uint32_t s0 = d.seed_off[g0], s1 = d.seed_off[g1];
+        d.view_seeds[v] = s1 - s0;
+        d.view_cand[v] = d.cand_pos[min(s1, ns)] - d.cand_pos[min(s0, ns)];
+    }
     for (uint32_t s = grid_tid(); s < ns; s += grid_threads()) {
         const uint32_t n = d.seed_n[s];
         if (!n) continue;
@@ -1107,25 +1087,9 @@ __global__ void __launch_bounds__(kBlock) k_cand_scatter(DevPtrs d, Caps c) {
         cd.n = n;
         cd.v = d.view_of[pq.x];
         d.cand[pos] = cd;
+        d.cand_n[pos] = n;
         d.key[pos] = cand_key(n, (uint32_t)d.sg[pq.x].w, (uint32_t)d.sg[pq.y].w);
     }
-}
-
-// Seeds and candidates of each view, from the offsets (views are contiguous
-// in anchor order, so in seed and in candidate order too).
-__global__ void k_view_counts(DevPtrs d, Caps c) {
-    const uint32_t v = grid_tid();
-    if (v >= d.desc->n_views) return;
-    const uint32_t g0 = d.grids[v].grain_off, g1 = g0 + d.grids[v].n;
-    const uint32_t ns = min(d.cnt->n_seeds, (uint32_t)c.seed_cap);
-    const uint32_t s0 = d.seed_off[g0], s1 = d.seed_off[g1];
-    d.view_seeds[v] = s1 - s0;
-    d.view_cand[v] = d.cand_pos[min(s1, ns)] - d.cand_pos[min(s0, ns)];
-}
-
-__global__ void __launch_bounds__(kBlock) k_cand_n(DevPtrs d, Caps c) {
-    const uint32_t nc = min(d.cnt->n_cand, c.cand_cap);
-    for (uint32_t i = grid_tid(); i < nc; i += grid_threads()) d.cand_n[i] = d.cand[i].n;
 }
 
 // ----------------------------------------------------------------- merge
@@ -1147,7 +1111,7 @@ __global__ void __launch_bounds__(kBlock) k_cand_n(DevPtrs d, Caps c) {
 // reserve into one pass; the tail kernel keeps the three phases.
 
 constexpr int kMaxRounds = 256;
-constexpr int kWideRounds = 16;  // grid-wide rounds (distinct key tags) before the tail
+constexpr int kWideRounds = 16;  // most grid-wide rounds (distinct key tags) before the tail
 
 __global__ void __launch_bounds__(kBlock) k_merge_init(DevPtrs d, Caps c) {
     const Counters *cn = d.cnt;
@@ -1168,7 +1132,6 @@ __global__ void __launch_bounds__(kBlock) k_merge_init(DevPtrs d, Caps c) {
     for (uint32_t r = grid_tid(); r < kMaxRounds; r += grid_threads()) d.undecided[r] = 0;
     if (grid_tid() == 0) {
         d.cnt->n_act[0] = nc;  // candidates taking part in the merge
-        d.cnt->n_act[1] = 0;
         d.cnt->err |= overflow ? 1u : 0u;
     }
 }
@@ -1737,18 +1700,12 @@ void launch_bin(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s)
 void launch_seeds(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
     const uint32_t nb = blocks_for(64ull * c.n_total, 4 * kPersistentBlocks);
     k_seeds<false><<<nb, kBlock, 0, s>>>(d, c, P);
-    scan_excl(d.seed_cnt, &d.desc->n_total, c.n_total, d.scan_part, d.seed_off, nullptr, s);
-    k_seed_total<<<1, 64, 0, s>>>(d, c);
+    // the scan total counts every seed (it wraps only above 2^32 - 1 a call)
+    scan_excl(d.seed_cnt, &d.desc->n_total, c.n_total, d.scan_part, d.seed_off, &d.cnt->n_seeds, s);
     k_seeds<true><<<nb, kBlock, 0, s>>>(d, c, P);
 }
 
 void launch_count(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
-    if (P.count_lanes >= 2) {
-        // batch form: 64 seeds per wave, kept for comparison runs
-        const uint32_t nb = blocks_for(c.seed_cap, kPersistentBlocks);
-        k_lines<false, 1><<<nb, kBlock, 0, s>>>(d, c, P);
-        return;
-    }
     k_count<<<kCountBlocks, kBlock, 0, s>>>(d, c, P);
 }
 
@@ -1756,13 +1713,13 @@ void launch_candidates(const DevPtrs &d, const Caps &c, const Params &, hipStrea
     scan_excl<true>(d.seed_n, &d.cnt->n_seeds, (uint32_t)c.seed_cap, d.scan_part, d.cand_pos,
                     &d.cnt->n_cand, s);
     k_cand_scatter<<<blocks_for(c.seed_cap, kPersistentBlocks), kBlock, 0, s>>>(d, c);
-    k_view_counts<<<(c.n_views + 63) / 64, 64, 0, s>>>(d, c);
 }
 
 void launch_members(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
-    k_cand_n<<<blocks_for(c.cand_cap, 1024), kBlock, 0, s>>>(d, c);
     scan_excl(d.cand_n, &d.cnt->n_cand, c.cand_cap, d.scan_part, d.mem_off, &d.cnt->n_members, s);
-    k_lines<true, 8><<<blocks_for(8ull * c.cand_cap, kPersistentBlocks), kBlock, 0, s>>>(d, c, P);
+    k_members<EMT_MEMBER_LANES><<<blocks_for((unsigned long long)EMT_MEMBER_LANES * c.cand_cap,
+                                            kPersistentBlocks),
+                                 kBlock, 0, s>>>(d, c, P);
 }
 
 void launch_merge_init(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {
@@ -1775,16 +1732,21 @@ void launch_merge_init(const DevPtrs &d, const Caps &c, const Params &, hipStrea
 void launch_merge(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
     // Later rounds see a fraction of the candidates: their grids shrink by
     // half per round down to a floor (the loops stride, so any grid is correct).
+    // The number of grid-wide rounds comes with the capacities (the host
+    // sizes it from the rounds earlier calls needed); the tail finishes
+    // whatever they leave.
+    const int wide = c.wide_rounds < 1 ? 1 : (c.wide_rounds > kWideRounds ? kWideRounds : c.wide_rounds);
     uint32_t nb = blocks_for((unsigned long long)kMergeGroup * c.cand_cap, 2 * kPersistentBlocks);
-    for (int round = 0; round < kWideRounds; ++round) {
+    for (int round = 0; round < wide; ++round) {
         k_round<0><<<nb, kBlock, 0, s>>>(d, P, round);
         k_round<1><<<nb, kBlock, 0, s>>>(d, P, round);
         if (round >= 1 && nb > 1024) nb = nb / 2 > 1024 ? nb / 2 : 1024;
     }
-    k_merge_tail<<<1, kTailBlock, 0, s>>>(d, P, kWideRounds - 1);
+    k_merge_tail<<<1, kTailBlock, 0, s>>>(d, P, wide - 1);
 }
 
 int max_merge_rounds() { return kMaxRounds; }
+int max_wide_rounds() { return kWideRounds; }
 
 void launch_copy_out(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {
     k_copy_out<<<64, kBlock, 0, s>>>(d, c);
