@@ -563,12 +563,13 @@ __device__ __forceinline__ bool xcd_grab(uint32_t *grab, uint32_t xcd, uint32_t 
 
 // ----------------------------------------------------------------- seeds
 //
-// One wave per anchor grain p; lanes take the (y, z) rows of the cell box
-// overlapping [g_p - (R-1), g_p + (R-1)]. Every grain q of those rows with a
-// higher input index and 0 < |g_q - g_p|^2 < R^2 makes a seed (p, q). A first
-// pass counts the seeds of every anchor, a scan turns the counts into
-// offsets, and a second pass writes them: no shared counter, and the seed
-// list comes out in anchor order.
+// One wave per anchor grain p (a sorted position); lanes take the (y, z)
+// rows of the cell box overlapping [g_p - (R-1), g_p + (R-1)]. Every grain q
+// of those rows at a higher sorted position with 0 < |g_q - g_p|^2 < R^2
+// makes a seed, stored with the lower input index first. A first pass counts
+// the seeds of every anchor, a scan turns the counts into offsets, and a
+// second pass writes them: no shared counter, and the seed list comes out in
+// anchor order, so each view's seeds are contiguous.
 template <bool kWrite>
 __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
     const int lane = lane_id();
@@ -592,21 +593,26 @@ __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
             const int x1 = min(nx - 1, (g.x + R1) / cx);
             const int y1 = min(ny - 1, (g.y + R1) / cy);
             const int z1 = min(nz - 1, (g.z + R1) / cz);
+            // each unordered pair once, from the grain with the lower sorted
+            // position: rows of the box that sort before the anchor's own row
+            // hold only lower positions, and in its row the scan starts past it
+            const int yp = min(ny - 1, g.y / cy), zp = min(nz - 1, g.z / cz);
             const int nyr = y1 - y0 + 1;
             const int nrows = nyr * (z1 - z0 + 1);
-            for (int rb = 0; rb < nrows; rb += 64) {
+            const int row_p = (zp - z0) * nyr + (yp - y0);
+            for (int rb = row_p; rb < nrows; rb += 64) {
                 const int rr = rb + lane;
                 uint32_t k0 = 0, k1 = 0;
                 if (rr < nrows) {
                     const int y = y0 + rr % nyr, z = z0 + rr / nyr;
                     const uint32_t row = off + (uint32_t)((z * ny + y) * nx);
-                    k0 = d.cell_start[row + x0];
+                    k0 = max(d.cell_start[row + x0], p + 1);
                     k1 = d.cell_start[row + x1 + 1];
                 }
                 for (uint32_t q = k0; q < k1; ++q) {
                     const int4 h = d.sg[q];
                     const int ex = h.x - g.x, ey = h.y - g.y, ez = h.z - g.z;
-                    bool ok = h.w > g.w && abs(ex) <= R1 && abs(ey) <= R1 && abs(ez) <= R1;
+                    bool ok = abs(ex) <= R1 && abs(ey) <= R1 && abs(ez) <= R1;
                     const int D = ok ? ex * ex + ey * ey + ez * ez : 0;
                     ok = ok && D > 0 && D < R2;
                     if (kWrite) {
@@ -614,7 +620,10 @@ __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
                         if (ok) {
                             const unsigned long long slot =
                                 (unsigned long long)base + (unsigned long long)__popcll(m & lanes_below());
-                            if (slot < c.seed_cap) d.seeds[slot] = make_uint2(p, q);
+                            // stored lower input index first: that grain is
+                            // the seed's i (the fit's origin and key order)
+                            if (slot < c.seed_cap)
+                                d.seeds[slot] = h.w > g.w ? make_uint2(p, q) : make_uint2(q, p);
                         }
                         base += (uint32_t)__popcll(m);
                     } else {
