@@ -347,15 +347,20 @@ struct Run {
 };
 
 struct Pencil {
-    // per line: x origin and direction, e/f axis data, parameter bounds
-    float gx, dx, gf, df, rr, tlo, thi, icx, icf;
-    float ue0, ues, uew;  // e cell j spans parameters [ue0 + j ues, + uew] (any order)
-    float uf0, ufs, ufw;  // f cell j likewise
-    int nx, ny, nf;
-    uint32_t off;
-    bool e_is_y;
+    // Per line, precomputed so a pencil costs few instructions: the line is
+    // oriented so that x grows with t; e and f cell intervals in t are stored
+    // low end first; x and f are kept in cell units (t * ds + gs) with the
+    // widening folded in; rows advance by fixed strides.
+    float tlo, thi;                  // t range within rr of the grid box
+    float ue_lo0, ue_step, ue_w;     // e cell j: t in [ue_lo0 + j ue_step, + ue_w]
+    float uf_lo0, uf_step, uf_w;     // f cell j likewise
+    float dfs, gfs, rrf, fnf;        // f in cell units, its widening, nf
+    float dxs, gxs_lo, gxs_hi, fnx;  // x in cell units minus / plus widening, nx
+    int nx, nf, ie1;
+    uint32_t off, se, sf;            // view's first cell, row strides of e and f
     // walk state: e cell ie of [.., ie1], f cells [jf, jf1] of it
-    int ie, ie1, jf, jf1;
+    int ie, jf, jf1;
+    uint32_t row_e;                  // off + ie * se
     float ta, tb;
     bool live;
 
@@ -365,20 +370,25 @@ struct Pencil {
     __device__ __forceinline__ void init(const ViewGrid *__restrict__ Gp, int4 g, int idx, int idy,
                                          int idz, int r, bool valid, int part, int nparts) {
         nx = Gp->dims[0];
-        ny = Gp->dims[1];
+        const int ny = Gp->dims[1];
         const int nz = Gp->dims[2];
         const int cxi = Gp->cell[0], cyi = Gp->cell[1], czi = Gp->cell[2];
         off = Gp->cell_off;
-        rr = (float)r + kMargin;
-        icx = __builtin_amdgcn_rcpf((float)cxi);
-        gx = (float)g.x;
-        dx = (float)idx;
+        const float rr = (float)r + kMargin;
+        // the line is undirected: take the direction with d_x >= 0
+        if (idx < 0) {
+            idx = -idx;
+            idy = -idy;
+            idz = -idz;
+        }
+        const float icx = __builtin_amdgcn_rcpf((float)cxi);
+        const float gx = (float)g.x, dx = (float)idx;
         const float gy = (float)g.y, gz = (float)g.z, dy = (float)idy, dz = (float)idz;
         const float ix = idx ? __builtin_amdgcn_rcpf(dx) : 0.0f;
         const float iy = idy ? __builtin_amdgcn_rcpf(dy) : 0.0f;
         const float iz = idz ? __builtin_amdgcn_rcpf(dz) : 0.0f;
         // parameter range in which the line is within rr of the grid box
-        constexpr float kBig = 3.0e38f;
+        constexpr float kBig = 1.0e38f;
         float t1, t2;
         tlo = -kBig;
         thi = kBig;
@@ -400,40 +410,53 @@ struct Pencil {
             tlo = fmaxf(tlo, fminf(t1, t2));
             thi = fminf(thi, fmaxf(t1, t2));
         }
-        e_is_y = abs(idy) >= abs(idz);
+        const bool e_is_y = abs(idy) >= abs(idz);
         const float ge = e_is_y ? gy : gz;
         const float de = e_is_y ? dy : dz;
         const float ie_ = e_is_y ? iy : iz;
         const float ce = (float)(e_is_y ? cyi : czi);
         const int ne = e_is_y ? ny : nz;
-        gf = e_is_y ? gz : gy;
-        df = e_is_y ? dz : dy;
+        const float gf = e_is_y ? gz : gy;
+        const float df = e_is_y ? dz : dy;
         const float if_ = e_is_y ? iz : iy;
         const float cf = (float)(e_is_y ? czi : cyi);
         nf = e_is_y ? nz : ny;
+        se = e_is_y ? (uint32_t)nx : (uint32_t)(nx * ny);
+        sf = e_is_y ? (uint32_t)(nx * ny) : (uint32_t)nx;
         const float ice = __builtin_amdgcn_rcpf(ce);
-        icf = __builtin_amdgcn_rcpf(cf);
+        const float icf = __builtin_amdgcn_rcpf(cf);
         // cell j of an axis with direction d != 0 is met for parameters
-        // [(j c - rr - g)/d, ((j+1) c - 1 + rr - g)/d]; with d == 0 every
-        // visited cell is met for all parameters
+        // between (j c - rr - g)/d and ((j+1) c - 1 + rr - g)/d, the first
+        // the lower one when d > 0; with d == 0 every visited cell is met for
+        // all parameters
         if (de != 0.0f) {
-            ue0 = (-rr - ge) * ie_;
-            ues = ce * ie_;
-            uew = (ce - 1.0f + 2.0f * rr) * ie_;
+            const float a0 = (-rr - ge) * ie_, w = (ce - 1.0f + 2.0f * rr) * ie_;
+            ue_step = ce * ie_;
+            ue_lo0 = de > 0.0f ? a0 : a0 + w;
+            ue_w = fabsf(w);
         } else {
-            ue0 = -kBig;
-            ues = 0.0f;
-            uew = 2.0f * kBig;
+            ue_lo0 = -kBig;
+            ue_step = 0.0f;
+            ue_w = 2.0f * kBig;
         }
         if (df != 0.0f) {
-            uf0 = (-rr - gf) * if_;
-            ufs = cf * if_;
-            ufw = (cf - 1.0f + 2.0f * rr) * if_;
+            const float a0 = (-rr - gf) * if_, w = (cf - 1.0f + 2.0f * rr) * if_;
+            uf_step = cf * if_;
+            uf_lo0 = df > 0.0f ? a0 : a0 + w;
+            uf_w = fabsf(w);
         } else {
-            uf0 = -kBig;
-            ufs = 0.0f;
-            ufw = 2.0f * kBig;
+            uf_lo0 = -kBig;
+            uf_step = 0.0f;
+            uf_w = 2.0f * kBig;
         }
+        dfs = df * icf;
+        gfs = gf * icf;
+        rrf = rr * icf;
+        fnf = (float)nf;
+        dxs = dx * icx;
+        gxs_lo = (gx - rr) * icx;
+        gxs_hi = (gx + rr) * icx;
+        fnx = (float)nx;
         // e cells the widened projection touches
         const float ea = ge + tlo * de, eb = ge + thi * de;
         const float elo = (de != 0.0f ? fminf(ea, eb) : ge) - rr;
@@ -449,6 +472,7 @@ struct Pencil {
         ie = ie0 - 1;
         jf = 1;
         jf1 = 0;
+        row_e = 0;
         ta = tb = 0.0f;
         live = valid && ie0 <= ie1 && tlo <= thi;
     }
@@ -456,36 +480,36 @@ struct Pencil {
     // One move of the walk, straight-line: step to the next e cell when the
     // current one is used up, then take the next f cell of it. Fills out
     // with that pencil's run or an empty run; the two cell_start loads are
-    // issued but not waited on.
+    // issued but not waited on. Truncation is the floor for lower bounds
+    // (clamped at 0); for upper ones it can only add a cell, which costs
+    // tests, not results.
     __device__ __forceinline__ void fetch(const uint32_t *__restrict__ cs, Run &out) {
         // set-up of e cell ie + 1, taken if the current one is used up
         const bool step_e = jf > jf1;
         const int ien = ie + 1;
-        const float e1 = fmaf((float)ien, ues, ue0), e2 = e1 + uew;
-        const float tan_ = fmaxf(tlo, fminf(e1, e2)), tbn = fminf(thi, fmaxf(e1, e2));
-        const float fa = fmaf(tan_, df, gf), fb = fmaf(tbn, df, gf);
-        // truncation is the floor for the lower bound (clamped at 0); for
-        // the upper one it can only add a cell, which costs tests, not results
-        const int jf0n = (int)fmaxf((fminf(fa, fb) - rr) * icf, 0.0f);
-        const int jf1n = min(nf - 1, (int)fmaxf(fminf((fmaxf(fa, fb) + rr) * icf, (float)nf), -1.0f));
+        const float elo = fmaf((float)ien, ue_step, ue_lo0);
+        const float tan_ = fmaxf(tlo, elo), tbn = fminf(thi, elo + ue_w);
+        const float fa = fmaf(tan_, dfs, gfs), fb = fmaf(tbn, dfs, gfs);
+        const int jf0n = (int)fmaxf(fminf(fa, fb) - rrf, 0.0f);
+        const int jf1n = min(nf - 1, (int)fmaxf(fminf(fmaxf(fa, fb) + rrf, fnf), -1.0f));
         if (step_e) {
             ie = ien;
             ta = tan_;
             tb = tbn;
             jf = tan_ <= tbn ? jf0n : 1;
             jf1 = tan_ <= tbn ? jf1n : 0;
+            row_e = off + (uint32_t)ien * se;
         }
         live = live && ie <= ie1;
         const int j = jf;
-        const float f1 = fmaf((float)j, ufs, uf0), f2 = f1 + ufw;
-        const float tc = fmaxf(ta, fminf(f1, f2)), td = fminf(tb, fmaxf(f1, f2));
-        const float xa = fmaf(tc, dx, gx), xb = fmaf(td, dx, gx);
-        const int x0 = (int)fmaxf((fminf(xa, xb) - rr) * icx, 0.0f);
-        const int x1 = min(nx - 1, (int)fmaxf(fminf((fmaxf(xa, xb) + rr) * icx, (float)nx), -1.0f));
+        const float flo = fmaf((float)j, uf_step, uf_lo0);
+        const float tc = fmaxf(ta, flo), td = fminf(tb, flo + uf_w);
+        // x grows with t, so [tc, td] maps to [x(tc), x(td)]
+        const int x0 = (int)fmaxf(fmaf(tc, dxs, gxs_lo), 0.0f);
+        const int x1 = min(nx - 1, (int)fmaxf(fminf(fmaf(td, dxs, gxs_hi), fnx), -1.0f));
         const bool ok = live && j <= jf1 && tc <= td && x0 <= x1;
         jf = j + 1;
-        const int iy = e_is_y ? ie : j, iz = e_is_y ? j : ie;
-        const uint32_t row = off + (uint32_t)((iz * ny + iy) * nx);
+        const uint32_t row = row_e + (uint32_t)j * sf;
         // 32-bit byte offsets from the table base (the table is far below
         // 4 GB), so the loads take a scalar base and one vector offset
         const char *base = reinterpret_cast<const char *>(cs);
