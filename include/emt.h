@@ -184,6 +184,40 @@ void emt_destroy(emt_ctx *ctx);
 const char *emt_strerror(int code);
 
 /*
+ * Grain recognition (paper, Sec. 2, grain recognition paragraph; Fig. 3c):
+ * the step before tracking. On a filtered stack of nz frames of ny rows of
+ * nx 8-bit pulse heights (x fastest), a pixel above the threshold defines a
+ * grain if no pixel of its 3 x 3 x 3 neighbourhood inside the stack is
+ * higher, or equal and earlier in frame, row, column order. The grain sits
+ * at the pulse-height centre of mass of that neighbourhood, pixel k of an
+ * axis being centred at k pitches: coordinates in 0.01 um units, rounded to
+ * the nearest unit (halves up) from exact integer sums, i.e. exactly the
+ * input of emt_track_views. Grains come out in frame, row, column order.
+ *
+ * geom: nx a multiple of 4 (4..65536), ny 1..65536, nz 1..4096, at most
+ * 2^31 pixels; threshold 0..255; pitch_num, pitch_den 1..65536 (the
+ * paper's 300 x 250 x 50 um view at 1280 x 1024 x 40 is 375/16, 3125/128,
+ * 125/1).
+ * stack: nx*ny*nz bytes, read during the call; xyz_out: room for max_out
+ * grains of 3 int32 (x, y, z). Both are host pointers, or device pointers
+ * (4-byte aligned, else EMT_EINVAL) if the context was created with
+ * EMT_F_DEVICE_PTRS. *n_out receives the
+ * number of grains found. Returns EMT_OK; EMT_EOVERFLOW if more than
+ * max_out grains were found (the first max_out are written);
+ * EMT_EINVAL/EMT_ERANGE for bad arguments; EMT_ENOMEM/EMT_EDEVICE.
+ */
+typedef struct {
+    uint32_t nx, ny, nz;
+    uint32_t threshold;
+    uint32_t pitch_num[3];
+    uint32_t pitch_den[3];
+} emt_stack_geom;
+
+int emt_find_grains(emt_ctx *ctx, const uint8_t *stack,
+                    const emt_stack_geom *geom, int32_t *xyz_out,
+                    uint32_t max_out, uint32_t *n_out);
+
+/*
  * Serving (paper, Sec. 3: the microscope delivers one view after another at
  * up to 5 Hz, and views are processed in parallel threads sharing the GPUs).
  * A server tracks views as they arrive. A worker thread runs n_pipes

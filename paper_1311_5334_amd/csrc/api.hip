@@ -53,6 +53,8 @@ struct emt_ctx {
 
     // device buffers, grown on demand
     DevArena grain_buf, cell_buf, seed_buf, cand_buf, mem_buf, view_buf, misc_buf;
+    DevArena stack_buf;  // grain recognition: stack copy, block counts, scan, output
+    uint32_t *h_small = nullptr;  // pinned: two words exchanged with the device
     DevPtrs d{};
     // capacities the buffers currently hold
     uint32_t cap_n = 0, cap_cells = 0, cap_views = 0, cap_cand = 0, cap_mem = 0;
@@ -884,6 +886,87 @@ int emt_track_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views, em
     return rc;
 }
 
+static int find_grains_impl(emt_ctx *ctx, const uint8_t *stack, const emt_stack_geom *g,
+                            int32_t *xyz_out, uint32_t max_out, uint32_t *n_out) {
+    if (!ctx || !g || !n_out) return EMT_EINVAL;
+    *n_out = 0;
+    if (ctx->poisoned) return EMT_EDEVICE;
+    if (g->nx < 4 || (g->nx & 3u) || g->nx > 65536u || g->ny < 1 || g->ny > 65536u ||
+        g->nz < 1 || g->nz > 4096u || g->threshold > 255u)
+        return EMT_ERANGE;
+    for (int m = 0; m < 3; ++m)
+        if (g->pitch_num[m] < 1 || g->pitch_num[m] > 65536u || g->pitch_den[m] < 1 ||
+            g->pitch_den[m] > 65536u)
+            return EMT_ERANGE;
+    const unsigned long long npix = (unsigned long long)g->nx * g->ny * g->nz;
+    if (npix > (1ull << 31)) return EMT_ERANGE;
+    if (!stack || (max_out > 0 && !xyz_out)) return EMT_EINVAL;
+    if (max_out > (1u << 28)) return EMT_ERANGE;
+    if (hipSetDevice(ctx->cfg.device) != hipSuccess) {
+        ctx->poisoned = true;
+        return EMT_EDEVICE;
+    }
+    const bool dev = (ctx->cfg.flags & EMT_F_DEVICE_PTRS) != 0;
+    // rows are read as aligned 32-bit words (host stacks are copied into an
+    // aligned buffer; device ones must start on a 4-byte boundary)
+    if (dev && ((uintptr_t)stack & 3u)) return EMT_EINVAL;
+    if (dev && max_out > 0 && ((uintptr_t)xyz_out & 3u)) return EMT_EINVAL;
+    StackGeom G{};
+    G.nx = g->nx;
+    G.ny = g->ny;
+    G.nz = g->nz;
+    G.thr = g->threshold;
+    for (int m = 0; m < 3; ++m) {
+        G.pnum[m] = g->pitch_num[m];
+        G.pden[m] = g->pitch_den[m];
+    }
+    const size_t nb = grain_block_count(G);
+    const size_t bytes = (dev ? 0 : bytes_of<uint8_t>((size_t)npix)) + bytes_of<uint32_t>(nb) +
+                         bytes_of<uint32_t>(nb + 1) +
+                         bytes_of<uint32_t>(scan_scratch_words((uint32_t)nb)) +
+                         bytes_of<uint32_t>(2) + (dev ? 0 : bytes_of<int32_t>(3 * (size_t)max_out));
+    int rc;
+    if ((rc = arena(ctx, ctx->stack_buf, bytes))) return rc;
+    size_t cap = 0;
+    if (!ctx->h_small && (rc = pinned(ctx, ctx->h_small, cap, 4))) return rc;
+    char *p = (char *)ctx->stack_buf.p;
+    const uint8_t *img = stack;
+    if (!dev) img = carve<uint8_t>(p, (size_t)npix);
+    GrainBufs b{};
+    b.block_cnt = carve<uint32_t>(p, nb);
+    b.block_off = carve<uint32_t>(p, nb + 1);
+    b.scan_part = carve<uint32_t>(p, scan_scratch_words((uint32_t)nb));
+    uint32_t *words = carve<uint32_t>(p, 2);
+    b.n_blocks = words;
+    b.total = words + 1;
+    b.out = dev ? xyz_out : carve<int32_t>(p, 3 * (size_t)max_out);
+    b.max_out = max_out;
+    hipStream_t s = ctx->stream;
+    if (!dev)
+        HIP_OK(hipMemcpyAsync((void *)img, stack, (size_t)npix, hipMemcpyHostToDevice, s));
+    ctx->h_small[0] = (uint32_t)nb;
+    HIP_OK(hipMemcpyAsync(b.n_blocks, ctx->h_small, sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    launch_find_grains(img, G, b, s);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(ctx->h_small + 1, b.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const uint32_t total = ctx->h_small[1];
+    *n_out = total;
+    const uint32_t n = total < max_out ? total : max_out;
+    if (!dev && n) {
+        HIP_OK(hipMemcpyAsync(xyz_out, b.out, 12 * (size_t)n, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+    }
+    return total > max_out ? EMT_EOVERFLOW : EMT_OK;
+}
+
+int emt_find_grains(emt_ctx *ctx, const uint8_t *stack, const emt_stack_geom *geom,
+                    int32_t *xyz_out, uint32_t max_out, uint32_t *n_out) {
+    const int rc = find_grains_impl(ctx, stack, geom, xyz_out, max_out, n_out);
+    (void)hipGetLastError();
+    return rc;
+}
+
 int emt_last_stats(emt_ctx *ctx, emt_call_stats *stats) {
     if (!ctx || !stats) return EMT_EINVAL;
     *stats = ctx->last;
@@ -896,10 +979,10 @@ void emt_destroy(emt_ctx *ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     drop_graphs(ctx);
     DevArena *arenas[] = {&ctx->grain_buf, &ctx->cell_buf, &ctx->seed_buf, &ctx->cand_buf,
-                          &ctx->mem_buf, &ctx->view_buf, &ctx->misc_buf};
+                          &ctx->mem_buf, &ctx->view_buf, &ctx->misc_buf, &ctx->stack_buf};
     for (DevArena *a : arenas)
         if (a->p) (void)hipFree(a->p);
-    void *hosts[] = {ctx->h_xyz, ctx->h_grids, ctx->h_desc, ctx->h.cnt, ctx->h.view_seeds,
+    void *hosts[] = {ctx->h_small, ctx->h_xyz, ctx->h_grids, ctx->h_desc, ctx->h.cnt, ctx->h.view_seeds,
                      ctx->h.view_cand, ctx->h.view_ntr, ctx->h.view_tr_off, ctx->h.view_err,
                      ctx->h.tracks, ctx->h.grains};
     for (void *p : hosts)

@@ -165,6 +165,27 @@ struct Caps {
     int32_t pad;
 };
 
+// Grain recognition: stack geometry and the device buffers of one call.
+struct StackGeom {
+    uint32_t nx, ny, nz;  // pixels per row, rows per frame, frames; nx % 4 == 0
+    uint32_t thr;         // pulse-height threshold (strict)
+    uint32_t pnum[3], pden[3];  // pitch of x, y, z in 0.01 um units: num/den
+};
+
+struct GrainBufs {
+    uint32_t *block_cnt;  // grain_block_count(G) entries
+    uint32_t *block_off;  // grain_block_count(G) + 1
+    uint32_t *scan_part;  // scan_scratch_words(grain_block_count(G))
+    uint32_t *n_blocks;   // device copy of grain_block_count(G)
+    uint32_t *total;      // grains found (may exceed max_out)
+    int32_t *out;         // 3 * max_out: x, y, z per grain, 0.01 um units
+    uint32_t max_out;
+};
+
+size_t grain_block_count(const StackGeom &G);
+void launch_find_grains(const uint8_t *img, const StackGeom &G, const GrainBufs &b,
+                        hipStream_t s);
+
 // Launchers (kernels.hip). All run on `s` and only enqueue work.
 void launch_prepare(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
 void launch_bin(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);

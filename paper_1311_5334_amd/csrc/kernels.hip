@@ -1691,6 +1691,129 @@ __global__ void __launch_bounds__(kBlock) k_copy_out(DevPtrs d, Caps c) {
     for (uint32_t i = tid; i < ng; i += nt) d.out.grains[i] = d.out_grains[i];
 }
 
+// ---------------------------------------------------- grain recognition
+//
+// 3D grain recognition on a filtered 8-bit stack (frames z, rows y, columns
+// x, x fastest): a pixel above the threshold that no in-stack 3 x 3 x 3
+// neighbour outranks (higher, or equal and earlier in frame, row, column
+// order) defines a grain, placed at the pulse-height centre of mass of its
+// block in 0.01 um units (pitch of each axis num/den units, rounded to the
+// nearest unit, halves up, from exact integer sums). One thread reads four
+// consecutive pixels of a row as one aligned 32-bit word, so a wave streams
+// 256 bytes of a row; the rare pixels above threshold read their
+// neighbours through the caches. A counting pass, a scan of per-workgroup
+// counts and a writing pass put the grains in frame, row, column order.
+
+__device__ __forceinline__ bool grain_at(const uint8_t *__restrict__ img, const StackGeom &G,
+                                         uint32_t x, uint32_t y, uint32_t z, uint32_t v) {
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int zz = (int)z + dz;
+        if (zz < 0 || zz >= (int)G.nz) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int yy = (int)y + dy;
+            if (yy < 0 || yy >= (int)G.ny) continue;
+            const size_t rowb = ((size_t)zz * G.ny + (size_t)yy) * G.nx;
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int xx = (int)x + dx;
+                if (xx < 0 || xx >= (int)G.nx || (dz == 0 && dy == 0 && dx == 0)) continue;
+                const uint32_t w = img[rowb + (size_t)xx];
+                const bool earlier = dz < 0 || (dz == 0 && (dy < 0 || (dy == 0 && dx < 0)));
+                if (w > v || (w == v && earlier)) return false;
+            }
+        }
+    }
+    return true;
+}
+
+template <bool kWrite>
+__global__ void __launch_bounds__(kBlock) k_grains(const uint8_t *__restrict__ img, StackGeom G,
+                                                   uint32_t *block_cnt,
+                                                   const uint32_t *__restrict__ block_off,
+                                                   int32_t *out, uint32_t max_out) {
+    __shared__ uint32_t s_wave[kBlock / 64];
+    const uint32_t gpr = G.nx >> 2;  // four-pixel groups per row
+    const unsigned long long n_groups = (unsigned long long)gpr * G.ny * G.nz;
+    const unsigned long long t = (unsigned long long)blockIdx.x * kBlock + threadIdx.x;
+    uint32_t found = 0, x4 = 0, y = 0, z = 0;
+    if (t < n_groups) {
+        const unsigned long long row = t / gpr;
+        x4 = (uint32_t)(t - row * gpr) * 4u;
+        y = (uint32_t)(row % G.ny);
+        z = (uint32_t)(row / G.ny);
+        const uint32_t word =
+            *reinterpret_cast<const uint32_t *>(img + (size_t)row * G.nx + x4);
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t v = (word >> (8 * k)) & 0xffu;
+            if (v > G.thr && grain_at(img, G, x4 + k, y, z, v)) found |= 1u << k;
+        }
+    }
+    // position of this thread's grains within the workgroup
+    const uint32_t mine = (uint32_t)__popc(found);
+    const uint32_t incl = wave_incl_scan_dpp(mine);
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    if (lane == 63) s_wave[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        before += w < wave ? s_wave[w] : 0u;
+        total += s_wave[w];
+    }
+    if (!kWrite) {
+        if (threadIdx.x == 0) block_cnt[blockIdx.x] = total;
+        return;
+    }
+    uint32_t pos = block_off[blockIdx.x] + before + incl - mine;
+    for (int k = 0; k < 4; ++k) {
+        if (!(found & (1u << k))) continue;
+        const uint32_t x = x4 + k;
+        int sw = 0, sx = 0, sy = 0, sz = 0;
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int zz = (int)z + dz;
+            if (zz < 0 || zz >= (int)G.nz) continue;
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int yy = (int)y + dy;
+                if (yy < 0 || yy >= (int)G.ny) continue;
+                const size_t rowb = ((size_t)zz * G.ny + (size_t)yy) * G.nx;
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int xx = (int)x + dx;
+                    if (xx < 0 || xx >= (int)G.nx) continue;
+                    const int w = img[rowb + (size_t)xx];
+                    sw += w;
+                    sx += w * xx;
+                    sy += w * yy;
+                    sz += w * zz;
+                }
+            }
+        }
+        if (pos < max_out) {
+            const int sums[3] = {sx, sy, sz};
+            for (int m = 0; m < 3; ++m) {
+                const long long num = 2ll * sums[m] * G.pnum[m] + (long long)sw * G.pden[m];
+                const long long den = 2ll * sw * G.pden[m];
+                out[3ull * pos + m] = (int32_t)(num / den);
+            }
+        }
+        ++pos;
+    }
+}
+
+}  // namespace
+
+size_t grain_block_count(const StackGeom &G) {
+    const unsigned long long groups = (unsigned long long)(G.nx >> 2) * G.ny * G.nz;
+    return (size_t)((groups + kBlock - 1) / kBlock);
+}
+
+void launch_find_grains(const uint8_t *img, const StackGeom &G, const GrainBufs &b,
+                        hipStream_t s) {
+    const uint32_t nb = (uint32_t)grain_block_count(G);
+    k_grains<false><<<nb, kBlock, 0, s>>>(img, G, b.block_cnt, nullptr, nullptr, 0);
+    scan_excl(b.block_cnt, b.n_blocks, nb, b.scan_part, b.block_off, b.total, s);
+    k_grains<true><<<nb, kBlock, 0, s>>>(img, G, nullptr, b.block_off, b.out, b.max_out);
+}
+
+namespace {
+
 uint32_t blocks_for(unsigned long long n, uint32_t max_blocks) {
     unsigned long long b = (n + kBlock - 1) / kBlock;
     if (b < 1) b = 1;

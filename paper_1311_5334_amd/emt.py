@@ -22,7 +22,10 @@ EMT_N_STAGES = len(STAGES)
 EXPORTS = ("emt_default_config", "emt_validate", "emt_create", "emt_track_views",
            "emt_last_stats", "emt_destroy", "emt_strerror", "emt_server_create",
            "emt_server_submit", "emt_server_poll", "emt_server_get_stats",
-           "emt_server_destroy")
+           "emt_server_destroy", "emt_find_grains")
+# the paper's view (300 x 250 x 50 um) at 1280 x 1024 x 40 pixels: pitches
+# in 0.01 um units as exact fractions
+PAPER_PITCH_NUM, PAPER_PITCH_DEN = (375, 3125, 125), (16, 128, 1)
 
 
 class EmtConfig(C.Structure):
@@ -61,6 +64,12 @@ class EmtCallStats(C.Structure):
                 ("merge_rounds", C.c_uint32), ("n_fp64_fits", C.c_uint32),
                 ("retries", C.c_uint32), ("n_views", C.c_uint32),
                 ("ms", C.c_float * EMT_N_STAGES), ("ms_total", C.c_float)]
+
+
+class EmtStackGeom(C.Structure):
+    _fields_ = [("nx", C.c_uint32), ("ny", C.c_uint32), ("nz", C.c_uint32),
+                ("threshold", C.c_uint32), ("pitch_num", C.c_uint32 * 3),
+                ("pitch_den", C.c_uint32 * 3)]
 
 
 class EmtServed(C.Structure):
@@ -131,6 +140,9 @@ def load(path: str = LIB_PATH):
     lib.emt_server_get_stats.restype = C.c_int
     lib.emt_server_destroy.argtypes = [C.c_void_p]
     lib.emt_server_destroy.restype = None
+    lib.emt_find_grains.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(EmtStackGeom), C.c_void_p,
+                                    C.c_uint32, C.POINTER(C.c_uint32)]
+    lib.emt_find_grains.restype = C.c_int
     _lib = lib
     return lib
 
@@ -219,6 +231,55 @@ def emt_track_views(ctx, views, device_ptrs: bool = False):
     return res
 
 
+def stack_geom(shape_zyx, threshold: int, pitch_num=PAPER_PITCH_NUM,
+               pitch_den=PAPER_PITCH_DEN) -> EmtStackGeom:
+    g = EmtStackGeom()
+    g.nz, g.ny, g.nx = (int(v) for v in shape_zyx)
+    g.threshold = threshold
+    g.pitch_num = (C.c_uint32 * 3)(*pitch_num)
+    g.pitch_den = (C.c_uint32 * 3)(*pitch_den)
+    return g
+
+
+def emt_find_grains(ctx, stack, threshold: int, device_ptrs: bool = False, max_out=None,
+                    pitch_num=PAPER_PITCH_NUM, pitch_den=PAPER_PITCH_DEN, out=None):
+    """Grains of a (nz, ny, nx) uint8 stack: a numpy array, or a contiguous
+    uint8 CUDA tensor when the context reads device pointers. Returns an
+    (n, 3) int32 array (host) or the first n rows of ``out`` / a new int32
+    CUDA tensor (device)."""
+    lib = load()
+    g = stack_geom(stack.shape, threshold, pitch_num, pitch_den)
+    n = C.c_uint32()
+    if device_ptrs:
+        import torch
+        if not (stack.is_cuda and stack.dtype == torch.uint8 and stack.is_contiguous()):
+            raise TypeError("device stacks must be contiguous uint8 CUDA tensors")
+        cap = max_out if max_out is not None else max(1024, stack.numel() // 64)
+        if out is None:
+            out = torch.empty((cap, 3), dtype=torch.int32, device=stack.device)
+        cap = min(cap, out.shape[0])
+        rc = lib.emt_find_grains(ctx, stack.data_ptr(), C.byref(g), out.data_ptr(), cap,
+                                 C.byref(n))
+        if rc == EMT_EOVERFLOW and max_out is None:
+            out = torch.empty((n.value, 3), dtype=torch.int32, device=stack.device)
+            rc = lib.emt_find_grains(ctx, stack.data_ptr(), C.byref(g), out.data_ptr(),
+                                     n.value, C.byref(n))
+        if rc != EMT_OK:
+            raise EmtError(rc, "emt_find_grains")
+        return out[:n.value]
+    a = np.ascontiguousarray(np.asarray(stack, dtype=np.uint8))
+    cap = max_out if max_out is not None else max(1024, a.size // 64)
+    buf = np.zeros((max(cap, 1), 3), np.int32)
+    rc = lib.emt_find_grains(ctx, a.ctypes.data, C.byref(g), buf.ctypes.data, cap, C.byref(n))
+    if rc == EMT_EOVERFLOW and max_out is None:
+        buf = np.zeros((n.value, 3), np.int32)
+        rc = lib.emt_find_grains(ctx, a.ctypes.data, C.byref(g), buf.ctypes.data, n.value,
+                                 C.byref(n))
+    if rc != EMT_OK:
+        raise EmtError(rc, "emt_find_grains")
+    return buf[:n.value].copy()
+
+
 def emt_last_stats(ctx) -> dict:
     st = EmtCallStats()
     rc = load().emt_last_stats(ctx, C.byref(st))
@@ -247,6 +308,9 @@ class Tracker:
 
     def stats(self) -> dict:
         return emt_last_stats(self.ctx)
+
+    def find_grains(self, stack, threshold: int, **kw):
+        return emt_find_grains(self.ctx, stack, threshold, self.device_ptrs, **kw)
 
     def close(self):
         if self.ctx is not None:

@@ -47,7 +47,8 @@ def test_struct_layout_matches_header(emt):
 #define O(t, f) printf(#t "." #f " %zu\n", offsetof(t, f));
 int main(void) {
   S(emt_config) S(emt_view_in) S(emt_track) S(emt_view_stats) S(emt_view_out) S(emt_call_stats)
-  S(emt_served) S(emt_server_stats)
+  S(emt_served) S(emt_server_stats) S(emt_stack_geom)
+  O(emt_stack_geom, threshold) O(emt_stack_geom, pitch_den)
   O(emt_config, hbm_budget) O(emt_config, stream) O(emt_track, slope) O(emt_track, t_end)
   O(emt_view_out, tracks) O(emt_view_out, stats) O(emt_call_stats, ms) O(emt_call_stats, ms_total)
   O(emt_served, tracks) O(emt_served, stats) O(emt_served, t_done_ms)
@@ -75,6 +76,9 @@ int main(void) {
         "emt_call_stats.ms": emt.EmtCallStats.ms.offset,
         "emt_call_stats.ms_total": emt.EmtCallStats.ms_total.offset,
         "emt_served": C.sizeof(emt.EmtServed), "emt_server_stats": C.sizeof(emt.EmtServerStats),
+        "emt_stack_geom": C.sizeof(emt.EmtStackGeom),
+        "emt_stack_geom.threshold": emt.EmtStackGeom.threshold.offset,
+        "emt_stack_geom.pitch_den": emt.EmtStackGeom.pitch_den.offset,
         "emt_served.tracks": emt.EmtServed.tracks.offset,
         "emt_served.stats": emt.EmtServed.stats.offset,
         "emt_served.t_done_ms": emt.EmtServed.t_done_ms.offset,
@@ -163,3 +167,11 @@ def test_server_rejects_bad_arguments_without_device(emt):
     assert lib.emt_server_poll(None, None, 0, C.byref(n), 0) == -1
     assert lib.emt_server_get_stats(None, None) == -1
     lib.emt_server_destroy(None)
+
+
+def test_find_grains_rejects_null_without_device(emt):
+    lib = emt.load()
+    n = C.c_uint32(7)
+    g = emt.stack_geom((4, 8, 16), 60)
+    assert lib.emt_find_grains(None, None, C.byref(g), None, 0, C.byref(n)) == -1
+    assert lib.emt_find_grains(None, None, None, None, 0, None) == -1
