@@ -174,7 +174,9 @@ int emt_create(const emt_config *cfg, emt_ctx **out);
 int emt_track_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views,
                     emt_view_out *out);
 
-/* Statistics of the last successful emt_track_views. */
+/* Statistics of the last successful emt_track_views. After emt_find_grains
+ * with EMT_F_STATS, every field is 0 except ms_total: the device time of the
+ * recognition kernels. */
 int emt_last_stats(emt_ctx *ctx, emt_call_stats *stats);
 
 /* Release a context; NULL is ignored. */
@@ -200,8 +202,8 @@ const char *emt_strerror(int code);
  * 125/1).
  * stack: nx*ny*nz bytes, read during the call; xyz_out: room for max_out
  * grains of 3 int32 (x, y, z). Both are host pointers, or device pointers
- * (4-byte aligned, else EMT_EINVAL) if the context was created with
- * EMT_F_DEVICE_PTRS. *n_out receives the
+ * (stack 16-byte and xyz_out 4-byte aligned, else EMT_EINVAL) if the
+ * context was created with EMT_F_DEVICE_PTRS. *n_out receives the
  * number of grains found. Returns EMT_OK; EMT_EOVERFLOW if more than
  * max_out grains were found (the first max_out are written);
  * EMT_EINVAL/EMT_ERANGE for bad arguments; EMT_ENOMEM/EMT_EDEVICE.

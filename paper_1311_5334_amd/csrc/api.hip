@@ -899,7 +899,7 @@ static int find_grains_impl(emt_ctx *ctx, const uint8_t *stack, const emt_stack_
             g->pitch_den[m] > 65536u)
             return EMT_ERANGE;
     const unsigned long long npix = (unsigned long long)g->nx * g->ny * g->nz;
-    if (npix > (1ull << 31)) return EMT_ERANGE;
+    if (npix > (1ull << 31)) return EMT_ERANGE;  // four-pixel groups then fit 32 bits
     if (!stack || (max_out > 0 && !xyz_out)) return EMT_EINVAL;
     if (max_out > (1u << 28)) return EMT_ERANGE;
     if (hipSetDevice(ctx->cfg.device) != hipSuccess) {
@@ -907,9 +907,9 @@ static int find_grains_impl(emt_ctx *ctx, const uint8_t *stack, const emt_stack_
         return EMT_EDEVICE;
     }
     const bool dev = (ctx->cfg.flags & EMT_F_DEVICE_PTRS) != 0;
-    // rows are read as aligned 32-bit words (host stacks are copied into an
-    // aligned buffer; device ones must start on a 4-byte boundary)
-    if (dev && ((uintptr_t)stack & 3u)) return EMT_EINVAL;
+    // the stack is read as aligned 16-byte vectors (host stacks are copied
+    // into an aligned buffer; device ones must start on a 16-byte boundary)
+    if (dev && ((uintptr_t)stack & 15u)) return EMT_EINVAL;
     if (dev && max_out > 0 && ((uintptr_t)xyz_out & 3u)) return EMT_EINVAL;
     StackGeom G{};
     G.nx = g->nx;
@@ -920,6 +920,8 @@ static int find_grains_impl(emt_ctx *ctx, const uint8_t *stack, const emt_stack_
         G.pnum[m] = g->pitch_num[m];
         G.pden[m] = g->pitch_den[m];
     }
+    G.inv_nx = 1.0 / (double)G.nx;
+    G.inv_ny = 1.0 / (double)G.ny;
     const size_t nb = grain_block_count(G);
     const size_t bytes = (dev ? 0 : bytes_of<uint8_t>((size_t)npix)) + bytes_of<uint32_t>(nb) +
                          bytes_of<uint32_t>(nb + 1) +
@@ -946,12 +948,17 @@ static int find_grains_impl(emt_ctx *ctx, const uint8_t *stack, const emt_stack_
         HIP_OK(hipMemcpyAsync((void *)img, stack, (size_t)npix, hipMemcpyHostToDevice, s));
     ctx->h_small[0] = (uint32_t)nb;
     HIP_OK(hipMemcpyAsync(b.n_blocks, ctx->h_small, sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    const bool stats = (ctx->cfg.flags & EMT_F_STATS) != 0;
+    if (stats) HIP_OK(hipEventRecord(ctx->ev[0], s));
     launch_find_grains(img, G, b, s);
     HIP_OK(hipGetLastError());
+    if (stats) HIP_OK(hipEventRecord(ctx->ev[1], s));
     HIP_OK(hipMemcpyAsync(ctx->h_small + 1, b.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     const uint32_t total = ctx->h_small[1];
     *n_out = total;
+    ctx->last = emt_call_stats{};
+    if (stats) (void)hipEventElapsedTime(&ctx->last.ms_total, ctx->ev[0], ctx->ev[1]);
     const uint32_t n = total < max_out ? total : max_out;
     if (!dev && n) {
         HIP_OK(hipMemcpyAsync(xyz_out, b.out, 12 * (size_t)n, hipMemcpyDeviceToHost, s));

@@ -170,6 +170,7 @@ struct StackGeom {
     uint32_t nx, ny, nz;  // pixels per row, rows per frame, frames; nx % 4 == 0
     uint32_t thr;         // pulse-height threshold (strict)
     uint32_t pnum[3], pden[3];  // pitch of x, y, z in 0.01 um units: num/den
+    double inv_nx, inv_ny;      // 1 / nx, 1 / ny
 };
 
 struct GrainBufs {

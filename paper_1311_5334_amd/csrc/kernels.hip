@@ -1704,25 +1704,87 @@ __global__ void __launch_bounds__(kBlock) k_copy_out(DevPtrs d, Caps c) {
 // neighbours through the caches. A counting pass, a scan of per-workgroup
 // counts and a writing pass put the grains in frame, row, column order.
 
-__device__ __forceinline__ bool grain_at(const uint8_t *__restrict__ img, const StackGeom &G,
-                                         uint32_t x, uint32_t y, uint32_t z, uint32_t v) {
-    for (int dz = -1; dz <= 1; ++dz) {
-        const int zz = (int)z + dz;
-        if (zz < 0 || zz >= (int)G.nz) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int yy = (int)y + dy;
-            if (yy < 0 || yy >= (int)G.ny) continue;
-            const size_t rowb = ((size_t)zz * G.ny + (size_t)yy) * G.nx;
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int xx = (int)x + dx;
-                if (xx < 0 || xx >= (int)G.nx || (dz == 0 && dy == 0 && dx == 0)) continue;
-                const uint32_t w = img[rowb + (size_t)xx];
-                const bool earlier = dz < 0 || (dz == 0 && (dy < 0 || (dy == 0 && dx < 0)));
-                if (w > v || (w == v && earlier)) return false;
-            }
+// q = n / d for n < 2^32, d >= 1: double-precision reciprocal, then an
+// exact integer correction of the +-1 it may be off by.
+__device__ __forceinline__ uint32_t div_rcp(uint32_t n, uint32_t d, double inv) {
+    uint32_t q = (uint32_t)((double)n * inv);
+    if ((unsigned long long)q * d > n) --q;
+    if ((unsigned long long)(q + 1) * d <= n) ++q;
+    return q;
+}
+
+// A thread streams kGrainWords consecutive four-pixel words (the stack is
+// one flat byte array, so they are contiguous across row ends too) as
+// 16-byte vectors and marks the pixels above threshold. The workgroup
+// lists its candidates in LDS, in pixel order, and then tests them one per
+// thread: few pixels pass the threshold, so this keeps the neighbourhood
+// tests dense instead of leaving most lanes of a wave idle.
+constexpr uint32_t kGrainWords = 8;     // 32 pixels a thread, one bit each
+constexpr uint32_t kCandCap = 2048;     // candidates listed per round
+
+__device__ __forceinline__ uint32_t block_excl_scan_small(uint32_t v, uint32_t *s_wave,
+                                                          uint32_t *total) {
+    const uint32_t incl = wave_incl_scan_dpp(v);
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    if (lane == 63) s_wave[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        before += w < wave ? s_wave[w] : 0u;
+        tot += s_wave[w];
+    }
+    __syncthreads();  // s_wave is reused by the next scan
+    *total = tot;
+    return before + incl - v;
+}
+
+// Pixel p (flat index) of the stack: is it a grain? If so and out is set,
+// its centre of mass is written there.
+__device__ __forceinline__ bool grain_test(const uint8_t *__restrict__ img, const StackGeom &G,
+                                           uint32_t p, int32_t *out) {
+    const uint32_t row = div_rcp(p, G.nx, G.inv_nx);
+    const uint32_t x = p - row * G.nx;
+    const uint32_t z = div_rcp(row, G.ny, G.inv_ny);
+    const uint32_t y = row - z * G.ny;
+    const uint32_t v = img[p];
+    uint32_t w[27];
+    uint32_t inside = 0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int zz = (int)z + i / 9 - 1, yy = (int)y + (i / 3) % 3 - 1, xx = (int)x + i % 3 - 1;
+        const bool ok = zz >= 0 && zz < (int)G.nz && yy >= 0 && yy < (int)G.ny && xx >= 0 &&
+                        xx < (int)G.nx;
+        inside |= ok ? 1u << i : 0u;
+        // every address stays inside the stack, whether or not it is read
+        const size_t q = ok ? ((size_t)zz * G.ny + (size_t)yy) * G.nx + (size_t)xx : (size_t)p;
+        w[i] = ok ? (uint32_t)img[q] : 0u;
+    }
+    bool top = true;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        if (i == 13) continue;
+        // neighbours 0..12 come earlier in frame, row, column order
+        const bool outranks = w[i] > v || (w[i] == v && i < 13);
+        top = top && !(((inside >> i) & 1u) && outranks);
+    }
+    if (top && out) {
+        int sw = 0, sx = 0, sy = 0, sz = 0;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const int wi = (int)w[i];  // 0 outside the stack
+            sw += wi;
+            sx += wi * ((int)x + i % 3 - 1);
+            sy += wi * ((int)y + (i / 3) % 3 - 1);
+            sz += wi * ((int)z + i / 9 - 1);
+        }
+        const int sums[3] = {sx, sy, sz};
+        for (int m = 0; m < 3; ++m) {
+            const long long num = 2ll * sums[m] * G.pnum[m] + (long long)sw * G.pden[m];
+            const long long den = 2ll * sw * G.pden[m];
+            out[m] = (int32_t)(num / den);
         }
     }
-    return true;
+    return top;
 }
 
 template <bool kWrite>
@@ -1731,77 +1793,74 @@ __global__ void __launch_bounds__(kBlock) k_grains(const uint8_t *__restrict__ i
                                                    const uint32_t *__restrict__ block_off,
                                                    int32_t *out, uint32_t max_out) {
     __shared__ uint32_t s_wave[kBlock / 64];
-    const uint32_t gpr = G.nx >> 2;  // four-pixel groups per row
-    const unsigned long long n_groups = (unsigned long long)gpr * G.ny * G.nz;
-    const unsigned long long t = (unsigned long long)blockIdx.x * kBlock + threadIdx.x;
-    uint32_t found = 0, x4 = 0, y = 0, z = 0;
-    if (t < n_groups) {
-        const unsigned long long row = t / gpr;
-        x4 = (uint32_t)(t - row * gpr) * 4u;
-        y = (uint32_t)(row % G.ny);
-        z = (uint32_t)(row / G.ny);
-        const uint32_t word =
-            *reinterpret_cast<const uint32_t *>(img + (size_t)row * G.nx + x4);
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t v = (word >> (8 * k)) & 0xffu;
-            if (v > G.thr && grain_at(img, G, x4 + k, y, z, v)) found |= 1u << k;
+    __shared__ uint32_t s_cand[kCandCap];
+    const uint32_t n_groups = (G.nx >> 2) * G.ny * G.nz;
+    const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) * kGrainWords;
+    uint32_t words[kGrainWords];
+    if (g0 + kGrainWords <= n_groups) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(img + 4ull * g0);
+#pragma unroll
+        for (int h = 0; h < (int)kGrainWords / 4; ++h) {
+            const uint4 q = p[h];
+            words[4 * h] = q.x;
+            words[4 * h + 1] = q.y;
+            words[4 * h + 2] = q.z;
+            words[4 * h + 3] = q.w;
         }
+    } else {
+#pragma unroll
+        for (int k = 0; k < (int)kGrainWords; ++k)
+            words[k] = g0 + k < n_groups
+                           ? *reinterpret_cast<const uint32_t *>(img + 4ull * (g0 + k))
+                           : 0u;
     }
-    // position of this thread's grains within the workgroup
-    const uint32_t mine = (uint32_t)__popc(found);
-    const uint32_t incl = wave_incl_scan_dpp(mine);
-    const int lane = lane_id(), wave = threadIdx.x >> 6;
-    if (lane == 63) s_wave[wave] = incl;
-    __syncthreads();
-    uint32_t before = 0, total = 0;
-    for (int w = 0; w < kBlock / 64; ++w) {
-        before += w < wave ? s_wave[w] : 0u;
-        total += s_wave[w];
-    }
-    if (!kWrite) {
-        if (threadIdx.x == 0) block_cnt[blockIdx.x] = total;
-        return;
-    }
-    uint32_t pos = block_off[blockIdx.x] + before + incl - mine;
-    for (int k = 0; k < 4; ++k) {
-        if (!(found & (1u << k))) continue;
-        const uint32_t x = x4 + k;
-        int sw = 0, sx = 0, sy = 0, sz = 0;
-        for (int dz = -1; dz <= 1; ++dz) {
-            const int zz = (int)z + dz;
-            if (zz < 0 || zz >= (int)G.nz) continue;
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int yy = (int)y + dy;
-                if (yy < 0 || yy >= (int)G.ny) continue;
-                const size_t rowb = ((size_t)zz * G.ny + (size_t)yy) * G.nx;
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int xx = (int)x + dx;
-                    if (xx < 0 || xx >= (int)G.nx) continue;
-                    const int w = img[rowb + (size_t)xx];
-                    sw += w;
-                    sx += w * xx;
-                    sy += w * yy;
-                    sz += w * zz;
-                }
+    uint32_t cand = 0;
+#pragma unroll
+    for (int k = 0; k < (int)kGrainWords; ++k)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            cand |= ((words[k] >> (8 * b)) & 0xffu) > G.thr ? 1u << (4 * k + b) : 0u;
+    uint32_t c_total;
+    const uint32_t c_before = block_excl_scan_small((uint32_t)__popc(cand), s_wave, &c_total);
+    uint32_t pos = kWrite ? block_off[blockIdx.x] : 0u;  // next grain of this workgroup
+    uint32_t found = 0;
+    for (uint32_t base = 0; base < c_total; base += kCandCap) {  // uniform
+        // list this round's candidates, in pixel order
+        uint32_t idx = c_before, bits = cand;
+        while (bits) {
+            const int i = __ffs((int)bits) - 1;
+            bits &= bits - 1;
+            if (idx >= base && idx < base + kCandCap) s_cand[idx - base] = 4u * g0 + (uint32_t)i;
+            ++idx;
+        }
+        __syncthreads();
+        const uint32_t m = min(kCandCap, c_total - base);
+        for (uint32_t c0 = 0; c0 < m; c0 += kBlock) {  // uniform
+            const uint32_t c = c0 + threadIdx.x;
+            int32_t xyz[3] = {0, 0, 0};
+            const bool top = c < m && grain_test(img, G, s_cand[c], kWrite ? xyz : nullptr);
+            uint32_t n_top;
+            const uint32_t before = block_excl_scan_small(top ? 1u : 0u, s_wave, &n_top);
+            if (kWrite && top && pos + before < max_out) {
+                int32_t *o = out + 3ull * (pos + before);
+                o[0] = xyz[0];
+                o[1] = xyz[1];
+                o[2] = xyz[2];
             }
+            pos += n_top;
+            found += n_top;
         }
-        if (pos < max_out) {
-            const int sums[3] = {sx, sy, sz};
-            for (int m = 0; m < 3; ++m) {
-                const long long num = 2ll * sums[m] * G.pnum[m] + (long long)sw * G.pden[m];
-                const long long den = 2ll * sw * G.pden[m];
-                out[3ull * pos + m] = (int32_t)(num / den);
-            }
-        }
-        ++pos;
+        __syncthreads();  // s_cand is rewritten by the next round
     }
+    if (!kWrite && threadIdx.x == 0) block_cnt[blockIdx.x] = found;
 }
 
 }  // namespace
 
 size_t grain_block_count(const StackGeom &G) {
     const unsigned long long groups = (unsigned long long)(G.nx >> 2) * G.ny * G.nz;
-    return (size_t)((groups + kBlock - 1) / kBlock);
+    const unsigned long long per_block = (unsigned long long)kBlock * kGrainWords;
+    return (size_t)((groups + per_block - 1) / per_block);
 }
 
 void launch_find_grains(const uint8_t *img, const StackGeom &G, const GrainBufs &b,
