@@ -922,11 +922,10 @@ static int find_grains_impl(emt_ctx *ctx, const uint8_t *stack, const emt_stack_
     }
     G.inv_nx = 1.0 / (double)G.nx;
     G.inv_ny = 1.0 / (double)G.ny;
-    const size_t nb = grain_block_count(G);
-    const size_t bytes = (dev ? 0 : bytes_of<uint8_t>((size_t)npix)) + bytes_of<uint32_t>(nb) +
-                         bytes_of<uint32_t>(nb + 1) +
-                         bytes_of<uint32_t>(scan_scratch_words((uint32_t)nb)) +
-                         bytes_of<uint32_t>(2) + (dev ? 0 : bytes_of<int32_t>(3 * (size_t)max_out));
+    const size_t nt = grain_tile_count(G), ng = grain_group_count(G);
+    const size_t bytes = (dev ? 0 : bytes_of<uint8_t>((size_t)npix)) + bytes_of<uint32_t>(nt) +
+                         bytes_of<uint32_t>(ng) + bytes_of<uint16_t>(grain_stage_slots(G)) +
+                         bytes_of<uint32_t>(1) + (dev ? 0 : bytes_of<int32_t>(3 * (size_t)max_out));
     int rc;
     if ((rc = arena(ctx, ctx->stack_buf, bytes))) return rc;
     size_t cap = 0;
@@ -935,19 +934,15 @@ static int find_grains_impl(emt_ctx *ctx, const uint8_t *stack, const emt_stack_
     const uint8_t *img = stack;
     if (!dev) img = carve<uint8_t>(p, (size_t)npix);
     GrainBufs b{};
-    b.block_cnt = carve<uint32_t>(p, nb);
-    b.block_off = carve<uint32_t>(p, nb + 1);
-    b.scan_part = carve<uint32_t>(p, scan_scratch_words((uint32_t)nb));
-    uint32_t *words = carve<uint32_t>(p, 2);
-    b.n_blocks = words;
-    b.total = words + 1;
+    b.tile_cnt = carve<uint32_t>(p, nt);
+    b.group_cnt = carve<uint32_t>(p, ng);
+    b.stage = carve<uint16_t>(p, grain_stage_slots(G));
+    b.total = carve<uint32_t>(p, 1);
     b.out = dev ? xyz_out : carve<int32_t>(p, 3 * (size_t)max_out);
     b.max_out = max_out;
     hipStream_t s = ctx->stream;
     if (!dev)
         HIP_OK(hipMemcpyAsync((void *)img, stack, (size_t)npix, hipMemcpyHostToDevice, s));
-    ctx->h_small[0] = (uint32_t)nb;
-    HIP_OK(hipMemcpyAsync(b.n_blocks, ctx->h_small, sizeof(uint32_t), hipMemcpyHostToDevice, s));
     const bool stats = (ctx->cfg.flags & EMT_F_STATS) != 0;
     if (stats) HIP_OK(hipEventRecord(ctx->ev[0], s));
     launch_find_grains(img, G, b, s);

@@ -174,16 +174,17 @@ struct StackGeom {
 };
 
 struct GrainBufs {
-    uint32_t *block_cnt;  // grain_block_count(G) entries
-    uint32_t *block_off;  // grain_block_count(G) + 1
-    uint32_t *scan_part;  // scan_scratch_words(grain_block_count(G))
-    uint32_t *n_blocks;   // device copy of grain_block_count(G)
+    uint32_t *tile_cnt;   // grains per tile, grain_tile_count(G) entries
+    uint32_t *group_cnt;  // grains per 64 tiles, grain_group_count(G) entries
+    uint16_t *stage;      // grain_stage_slots(G): grain offsets within their tile
     uint32_t *total;      // grains found (may exceed max_out)
     int32_t *out;         // 3 * max_out: x, y, z per grain, 0.01 um units
     uint32_t max_out;
 };
 
-size_t grain_block_count(const StackGeom &G);
+size_t grain_tile_count(const StackGeom &G);
+size_t grain_group_count(const StackGeom &G);
+size_t grain_stage_slots(const StackGeom &G);
 void launch_find_grains(const uint8_t *img, const StackGeom &G, const GrainBufs &b,
                         hipStream_t s);
 

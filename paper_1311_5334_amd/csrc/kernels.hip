@@ -1698,11 +1698,23 @@ __global__ void __launch_bounds__(kBlock) k_copy_out(DevPtrs d, Caps c) {
 // neighbour outranks (higher, or equal and earlier in frame, row, column
 // order) defines a grain, placed at the pulse-height centre of mass of its
 // block in 0.01 um units (pitch of each axis num/den units, rounded to the
-// nearest unit, halves up, from exact integer sums). One thread reads four
-// consecutive pixels of a row as one aligned 32-bit word, so a wave streams
-// 256 bytes of a row; the rare pixels above threshold read their
-// neighbours through the caches. A counting pass, a scan of per-workgroup
-// counts and a writing pass put the grains in frame, row, column order.
+// nearest unit, halves up, from exact integer sums).
+//
+// The stack is streamed once. A workgroup owns a tile of kTilePix
+// consecutive pixels (the stack is one flat byte array, so a tile runs
+// across row ends): each thread reads 32 of them as two 16-byte vectors and
+// marks those above threshold; the workgroup lists its candidates in LDS in
+// pixel order and tests them one per thread, which keeps the neighbourhood
+// tests dense although few pixels pass the threshold. The grains' offsets in
+// the tile go, in pixel order, to the tile's staging slots. Two pixels next
+// to each other in a row cannot both be grains (one outranks the other), and
+// tile and row boundaries fall on multiples of four pixels, so a tile holds
+// at most kTilePix / 2 grains: the staging area is bounded. Tile counts are
+// also summed per group of 64 tiles with one atomic add each. A second,
+// small kernel (one workgroup per group of tiles) takes its place in the
+// output from those sums, finds each staged grain's tile by a search over
+// the group's tile offsets, and writes the centre of mass: grains come out
+// in frame, row, column order without a separate scan or a second stream.
 
 // q = n / d for n < 2^32, d >= 1: double-precision reciprocal, then an
 // exact integer correction of the +-1 it may be off by.
@@ -1713,14 +1725,17 @@ __device__ __forceinline__ uint32_t div_rcp(uint32_t n, uint32_t d, double inv) 
     return q;
 }
 
-// A thread streams kGrainWords consecutive four-pixel words (the stack is
-// one flat byte array, so they are contiguous across row ends too) as
-// 16-byte vectors and marks the pixels above threshold. The workgroup
-// lists its candidates in LDS, in pixel order, and then tests them one per
-// thread: few pixels pass the threshold, so this keeps the neighbourhood
-// tests dense instead of leaving most lanes of a wave idle.
-constexpr uint32_t kGrainWords = 8;     // 32 pixels a thread, one bit each
-constexpr uint32_t kCandCap = 2048;     // candidates listed per round
+#ifndef EMT_GRAIN_WORDS
+#define EMT_GRAIN_WORDS 8
+#endif
+constexpr uint32_t kGrainWords = EMT_GRAIN_WORDS;           // four-pixel words a thread
+constexpr uint32_t kCandMasks = kGrainWords / 8;            // 32-pixel candidate masks
+static_assert(kGrainWords % 8 == 0, "candidate masks cover 32 pixels each");
+constexpr uint32_t kTilePix = kBlock * kGrainWords * 4;     // pixels a workgroup streams
+constexpr uint32_t kTileGrains = kTilePix / 2;              // staging slots per tile
+constexpr uint32_t kTileGroup = 64;                         // tiles per atomic sum
+constexpr uint32_t kCandCap = 2048;                         // candidates listed per round
+static_assert(kTilePix <= 65536u, "tile offsets are staged as 16 bits");
 
 __device__ __forceinline__ uint32_t block_excl_scan_small(uint32_t v, uint32_t *s_wave,
                                                           uint32_t *total) {
@@ -1738,63 +1753,89 @@ __device__ __forceinline__ uint32_t block_excl_scan_small(uint32_t v, uint32_t *
     return before + incl - v;
 }
 
-// Pixel p (flat index) of the stack: is it a grain? If so and out is set,
-// its centre of mass is written there.
-__device__ __forceinline__ bool grain_test(const uint8_t *__restrict__ img, const StackGeom &G,
-                                           uint32_t p, int32_t *out) {
-    const uint32_t row = div_rcp(p, G.nx, G.inv_nx);
-    const uint32_t x = p - row * G.nx;
-    const uint32_t z = div_rcp(row, G.ny, G.inv_ny);
-    const uint32_t y = row - z * G.ny;
-    const uint32_t v = img[p];
+// The 3 x 3 x 3 block around pixel p (flat index): pulse heights w[i]
+// (0 outside the stack) with i = 9 (dz+1) + 3 (dy+1) + (dx+1), so
+// neighbours 0..12 come before p in frame, row, column order.
+struct Block27 {
+    uint32_t x, y, z;
     uint32_t w[27];
-    uint32_t inside = 0;
+    uint32_t inside;
+
+    __device__ __forceinline__ void load(const uint8_t *__restrict__ img, const StackGeom &G,
+                                         uint32_t p) {
+        const uint32_t row = div_rcp(p, G.nx, G.inv_nx);
+        x = p - row * G.nx;
+        z = div_rcp(row, G.ny, G.inv_ny);
+        y = row - z * G.ny;
+        const uint32_t plane = G.nx * G.ny;  // at most 2^31 pixels: offsets fit 32 bits
+        // bit d + 1: the frame / row / column at offset d exists
+        const uint32_t zok = (z > 0 ? 1u : 0u) | 2u | (z + 1 < G.nz ? 4u : 0u);
+        const uint32_t yok = (y > 0 ? 1u : 0u) | 2u | (y + 1 < G.ny ? 4u : 0u);
+        const uint32_t xok = (x > 0 ? 1u : 0u) | 2u | (x + 1 < G.nx ? 4u : 0u);
+        inside = 0;
+        // all 27 loads are issued unconditionally (a missing neighbour reads
+        // pixel p itself, so every address is inside the stack) and masked
+        // afterwards: no branch or wait separates them
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const int zz = (int)z + i / 9 - 1, yy = (int)y + (i / 3) % 3 - 1, xx = (int)x + i % 3 - 1;
-        const bool ok = zz >= 0 && zz < (int)G.nz && yy >= 0 && yy < (int)G.ny && xx >= 0 &&
-                        xx < (int)G.nx;
-        inside |= ok ? 1u << i : 0u;
-        // every address stays inside the stack, whether or not it is read
-        const size_t q = ok ? ((size_t)zz * G.ny + (size_t)yy) * G.nx + (size_t)xx : (size_t)p;
-        w[i] = ok ? (uint32_t)img[q] : 0u;
+        for (int i = 0; i < 27; ++i) {
+            const int dz = i / 9 - 1, dy = (i / 3) % 3 - 1, dx = i % 3 - 1;
+            const bool ok = ((zok >> (dz + 1)) & (yok >> (dy + 1)) & (xok >> (dx + 1)) & 1u) != 0;
+            inside |= ok ? 1u << i : 0u;
+            // unsigned arithmetic wraps modulo 2^32 to the exact offset
+            const uint32_t q =
+                ok ? p + (uint32_t)dz * plane + (uint32_t)dy * G.nx + (uint32_t)dx : p;
+            // the mask is opaque to the compiler, which would otherwise
+            // turn "ok ? load : 0" back into a branch around the load
+            uint32_t mask = ok ? 0xffu : 0u;
+            asm("" : "+v"(mask));
+            w[i] = (uint32_t)img[q] & mask;
+        }
     }
-    bool top = true;
+    // No neighbour outranks the centre: higher, or equal and earlier. A
+    // missing neighbour reads 0 and the centre is above the threshold, so it
+    // never outranks. Bitwise, without short-circuits, so that every load is
+    // needed and none is moved into a branch.
+    __device__ __forceinline__ bool is_top() const {
+        const uint32_t v = w[13];
+        uint32_t beaten = 0;
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        if (i == 13) continue;
-        // neighbours 0..12 come earlier in frame, row, column order
-        const bool outranks = w[i] > v || (w[i] == v && i < 13);
-        top = top && !(((inside >> i) & 1u) && outranks);
+        for (int i = 0; i < 27; ++i) {
+            if (i < 13) beaten |= (uint32_t)(w[i] >= v);
+            if (i > 13) beaten |= (uint32_t)(w[i] > v);
+        }
+        return beaten == 0;
     }
-    if (top && out) {
+    __device__ __forceinline__ void centre(const StackGeom &G, int32_t *out) const {
         int sw = 0, sx = 0, sy = 0, sz = 0;
 #pragma unroll
         for (int i = 0; i < 27; ++i) {
-            const int wi = (int)w[i];  // 0 outside the stack
+            const int wi = (int)w[i];
             sw += wi;
             sx += wi * ((int)x + i % 3 - 1);
             sy += wi * ((int)y + (i / 3) % 3 - 1);
             sz += wi * ((int)z + i / 9 - 1);
         }
         const int sums[3] = {sx, sy, sz};
+#pragma unroll
         for (int m = 0; m < 3; ++m) {
+            // floor(num / den), num < 2^47 and 0 < den < 2^31: a double
+            // quotient is within one of it, and integer products fix that
             const long long num = 2ll * sums[m] * G.pnum[m] + (long long)sw * G.pden[m];
             const long long den = 2ll * sw * G.pden[m];
-            out[m] = (int32_t)(num / den);
+            long long q = (long long)((double)num / (double)den);
+            if (q * den > num) --q;
+            if ((q + 1) * den <= num) ++q;
+            out[m] = (int32_t)q;
         }
     }
-    return top;
-}
+};
 
-template <bool kWrite>
-__global__ void __launch_bounds__(kBlock) k_grains(const uint8_t *__restrict__ img, StackGeom G,
-                                                   uint32_t *block_cnt,
-                                                   const uint32_t *__restrict__ block_off,
-                                                   int32_t *out, uint32_t max_out) {
+__global__ void __launch_bounds__(kBlock) k_grain_find(const uint8_t *__restrict__ img,
+                                                       StackGeom G, uint32_t *tile_cnt,
+                                                       uint32_t *group_cnt, uint16_t *stage) {
     __shared__ uint32_t s_wave[kBlock / 64];
     __shared__ uint32_t s_cand[kCandCap];
-    const uint32_t n_groups = (G.nx >> 2) * G.ny * G.nz;
+    const uint32_t n_groups = (G.nx >> 2) * G.ny * G.nz;  // four-pixel words
     const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) * kGrainWords;
     uint32_t words[kGrainWords];
     if (g0 + kGrainWords <= n_groups) {
@@ -1814,61 +1855,130 @@ __global__ void __launch_bounds__(kBlock) k_grains(const uint8_t *__restrict__ i
                            ? *reinterpret_cast<const uint32_t *>(img + 4ull * (g0 + k))
                            : 0u;
     }
-    uint32_t cand = 0;
+    uint32_t cand[kCandMasks], n_cand = 0;
 #pragma unroll
-    for (int k = 0; k < (int)kGrainWords; ++k)
+    for (int j = 0; j < (int)kCandMasks; ++j) {
+        uint32_t c = 0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-            cand |= ((words[k] >> (8 * b)) & 0xffu) > G.thr ? 1u << (4 * k + b) : 0u;
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                c |= ((words[8 * j + k] >> (8 * b)) & 0xffu) > G.thr ? 1u << (4 * k + b) : 0u;
+        cand[j] = c;
+        n_cand += (uint32_t)__popc(c);
+    }
     uint32_t c_total;
-    const uint32_t c_before = block_excl_scan_small((uint32_t)__popc(cand), s_wave, &c_total);
-    uint32_t pos = kWrite ? block_off[blockIdx.x] : 0u;  // next grain of this workgroup
+    const uint32_t c_before = block_excl_scan_small(n_cand, s_wave, &c_total);
+    const uint32_t tile0 = blockIdx.x * kTilePix;
+    uint16_t *st = stage + (size_t)blockIdx.x * kTileGrains;
     uint32_t found = 0;
     for (uint32_t base = 0; base < c_total; base += kCandCap) {  // uniform
         // list this round's candidates, in pixel order
-        uint32_t idx = c_before, bits = cand;
-        while (bits) {
-            const int i = __ffs((int)bits) - 1;
-            bits &= bits - 1;
-            if (idx >= base && idx < base + kCandCap) s_cand[idx - base] = 4u * g0 + (uint32_t)i;
-            ++idx;
+        uint32_t idx = c_before;
+#pragma unroll
+        for (int j = 0; j < (int)kCandMasks; ++j) {
+            uint32_t bits = cand[j];
+            while (bits) {
+                const int i = __ffs((int)bits) - 1;
+                bits &= bits - 1;
+                if (idx >= base && idx < base + kCandCap)
+                    s_cand[idx - base] = 4u * g0 + 32u * (uint32_t)j + (uint32_t)i;
+                ++idx;
+            }
         }
         __syncthreads();
         const uint32_t m = min(kCandCap, c_total - base);
         for (uint32_t c0 = 0; c0 < m; c0 += kBlock) {  // uniform
             const uint32_t c = c0 + threadIdx.x;
-            int32_t xyz[3] = {0, 0, 0};
-            const bool top = c < m && grain_test(img, G, s_cand[c], kWrite ? xyz : nullptr);
+            bool top = false;
+            if (c < m) {
+                Block27 B;
+                B.load(img, G, s_cand[c]);
+                top = B.is_top();
+            }
             uint32_t n_top;
             const uint32_t before = block_excl_scan_small(top ? 1u : 0u, s_wave, &n_top);
-            if (kWrite && top && pos + before < max_out) {
-                int32_t *o = out + 3ull * (pos + before);
-                o[0] = xyz[0];
-                o[1] = xyz[1];
-                o[2] = xyz[2];
-            }
-            pos += n_top;
+            if (top && found + before < kTileGrains)  // always true: see the bound above
+                st[found + before] = (uint16_t)(s_cand[c] - tile0);
             found += n_top;
         }
         __syncthreads();  // s_cand is rewritten by the next round
     }
-    if (!kWrite && threadIdx.x == 0) block_cnt[blockIdx.x] = found;
+    if (threadIdx.x == 0) {
+        tile_cnt[blockIdx.x] = found;
+        if (found) atomicAdd(group_cnt + blockIdx.x / kTileGroup, found);
+    }
+}
+
+// One workgroup per group of kTileGroup tiles: its grains' place in the
+// output is the sum of the earlier groups' counts plus the offset of the
+// tile within the group.
+__global__ void __launch_bounds__(kBlock) k_grain_place(
+    const uint8_t *__restrict__ img, StackGeom G, const uint32_t *__restrict__ tile_cnt,
+    const uint32_t *__restrict__ group_cnt, uint32_t n_tiles,
+    const uint16_t *__restrict__ stage, int32_t *out, uint32_t max_out, uint32_t *total) {
+    static_assert(kTileGroup == 64, "tile offsets are scanned by one wave");
+    __shared__ uint32_t s_wave[kBlock / 64];
+    __shared__ uint32_t s_off[kTileGroup + 1];
+    const uint32_t grp = blockIdx.x;
+    uint32_t acc = 0;
+    for (uint32_t i = threadIdx.x; i < grp; i += kBlock) acc += group_cnt[i];
+    uint32_t prefix;
+    (void)block_excl_scan_small(acc, s_wave, &prefix);
+    const uint32_t t0 = grp * kTileGroup;
+    if (threadIdx.x < 64) {
+        const uint32_t t = t0 + threadIdx.x;
+        const uint32_t c = t < n_tiles ? min(tile_cnt[t], kTileGrains) : 0u;
+        s_off[threadIdx.x + 1] = wave_incl_scan_dpp(c);
+        if (threadIdx.x == 0) s_off[0] = 0;
+    }
+    __syncthreads();
+    const uint32_t n_here = s_off[kTileGroup];
+    if (grp + 1 == gridDim.x && threadIdx.x == 0) *total = prefix + n_here;
+    for (uint32_t g = threadIdx.x; g < n_here; g += kBlock) {
+        // the tile holding grain g: s_off[lo] <= g < s_off[lo + 1]
+        uint32_t lo = 0, hi = kTileGroup;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_off[mid] <= g) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t t = t0 + lo;
+        const uint32_t p = t * kTilePix + stage[(size_t)t * kTileGrains + (g - s_off[lo])];
+        const uint32_t q = prefix + g;
+        if (q < max_out) {
+            Block27 B;
+            B.load(img, G, p);
+            B.centre(G, out + 3ull * q);
+        }
+    }
+}
+
+__global__ void k_clear_words(uint32_t *p, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
 }
 
 }  // namespace
 
-size_t grain_block_count(const StackGeom &G) {
-    const unsigned long long groups = (unsigned long long)(G.nx >> 2) * G.ny * G.nz;
-    const unsigned long long per_block = (unsigned long long)kBlock * kGrainWords;
-    return (size_t)((groups + per_block - 1) / per_block);
+size_t grain_tile_count(const StackGeom &G) {
+    const unsigned long long pix = (unsigned long long)G.nx * G.ny * G.nz;
+    return (size_t)((pix + kTilePix - 1) / kTilePix);
 }
+
+size_t grain_group_count(const StackGeom &G) {
+    return (grain_tile_count(G) + kTileGroup - 1) / kTileGroup;
+}
+
+size_t grain_stage_slots(const StackGeom &G) { return grain_tile_count(G) * kTileGrains; }
 
 void launch_find_grains(const uint8_t *img, const StackGeom &G, const GrainBufs &b,
                         hipStream_t s) {
-    const uint32_t nb = (uint32_t)grain_block_count(G);
-    k_grains<false><<<nb, kBlock, 0, s>>>(img, G, b.block_cnt, nullptr, nullptr, 0);
-    scan_excl(b.block_cnt, b.n_blocks, nb, b.scan_part, b.block_off, b.total, s);
-    k_grains<true><<<nb, kBlock, 0, s>>>(img, G, nullptr, b.block_off, b.out, b.max_out);
+    const uint32_t nt = (uint32_t)grain_tile_count(G), ng = (uint32_t)grain_group_count(G);
+    k_clear_words<<<(ng + kBlock - 1) / kBlock, kBlock, 0, s>>>(b.group_cnt, ng);
+    k_grain_find<<<nt, kBlock, 0, s>>>(img, G, b.tile_cnt, b.group_cnt, b.stage);
+    k_grain_place<<<ng, kBlock, 0, s>>>(img, G, b.tile_cnt, b.group_cnt, nt, b.stage, b.out,
+                                        b.max_out, b.total);
 }
 
 namespace {

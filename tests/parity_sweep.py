@@ -6,9 +6,12 @@ views of every workload. Needs a GPU; pytest does not collect this file.
 Views (at --scale 1): c1 100, c2 32, c3 512 (8 calls of 64), c4 300 (tracked
 in calls of 16 views and, separately, as one stream through the server;
 the two must agree byte for byte), c5 32 (one call). Every view is compared
-with the oracle by tests/parity.py. The oracle runs in a pool of worker
-processes forked before the GPU is touched; the summary also gives the
-oracle's whole-pool rate (grains per second of wall time on those cores).
+with the oracle by tests/parity.py. Also 16 filtered stacks of the paper's
+1280x1024x40 view (fog 0.5-4 per 1000 um^3, thresholds 40-120) go through
+the grain recognition, whose grain lists must equal the oracle's exactly.
+The oracle runs in a pool of worker processes forked before the GPU is
+touched; the summary also gives the oracle's whole-pool tracking rate
+(grains per second of wall time on those cores).
 """
 from __future__ import annotations
 
@@ -28,6 +31,21 @@ sys.path.insert(0, HERE)
 from paper_1311_5334_amd import synth  # noqa: E402
 
 COUNTS = {"c5": 32, "c4": 300, "c3": 512, "c2": 32, "c1": 100}
+N_STACKS = 16
+
+
+def _stack(i):
+    from paper_1311_5334_amd import synth_stack
+    st = synth_stack.make_stack(i, fog_per_1000_um3=0.5 + 3.5 * (i % 4) / 3.0)
+    st.threshold = (40, 60, 90, 120)[(i // 4) % 4]
+    return st
+
+
+def _stack_job(i):
+    from oracle.grains import find_grains
+    st = _stack(i)
+    ref, _ = find_grains(st.img, st.threshold)
+    return i, ref
 
 
 def _oracle_job(job):
@@ -84,7 +102,17 @@ def main() -> int:
     pool = ctx.Pool(args.procs)
     t_pool = time.perf_counter()
     it = pool.imap_unordered(_oracle_job, jobs, chunksize=1)
+    n_st = max(1, int(N_STACKS * args.scale))
+    it_st = pool.imap_unordered(_stack_job, range(n_st), chunksize=1)
     got, served = _gpu_all(jobs)
+    from paper_1311_5334_amd import emt
+    st_fail, st_grains = 0, 0
+    with emt.Tracker(device=0) as tr:
+        st_got = {}
+        for i in range(n_st):
+            st = _stack(i)
+            st_got[i] = tr.find_grains(st.img, st.threshold)
+    print(f"gpu: {n_st} stacks recognised", flush=True)
     stats = {cfg: {"views": 0, "grains": 0, "cpu_s": 0.0, "fail": 0, "first": "", "tracks": 0}
              for cfg in COUNTS}
     serve_mismatch = 0
@@ -114,6 +142,11 @@ def main() -> int:
             print(f"oracle: {done}/{len(jobs)} views compared "
                   f"[{time.perf_counter() - t_pool:.0f} s]", flush=True)
     wall = time.perf_counter() - t_pool
+    for i, ref in it_st:
+        st_grains += len(ref)
+        if not np.array_equal(st_got[i], ref):
+            st_fail += 1
+    print(f"oracle: {n_st} stacks compared", flush=True)
     pool.close()
     pool.join()
     fails = sum(st["fail"] for st in stats.values())
@@ -136,6 +169,8 @@ def main() -> int:
     tot_cpu = sum(st["cpu_s"] for st in stats.values())
     lines += ["", f"Served c4 stream vs batched c4: {serve_mismatch} mismatching views of "
               f"{stats['c4']['views']}.", "",
+              f"Grain recognition: {n_st} stacks of 1280x1024x40 pixels, {st_grains:,} grains; "
+              f"{st_fail} stacks differ from the oracle's grain list.", "",
               f"Oracle: {tot_g:,} grains in {tot_cpu:.0f} s of single-thread CPU time "
               f"({tot_g / tot_cpu:,.0f} grains/s per core); {args.procs} worker processes "
               f"finished in {wall:.0f} s of wall time ({tot_g / wall:,.0f} grains/s for the "
@@ -147,7 +182,7 @@ def main() -> int:
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     open(args.out, "w").write(text)
     print(text, flush=True)
-    return 1 if fails or serve_mismatch else 0
+    return 1 if fails or serve_mismatch or st_fail else 0
 
 
 if __name__ == "__main__":
