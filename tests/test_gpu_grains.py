@@ -82,6 +82,66 @@ def test_full_view_matches_oracle_and_feeds_tracking(emt, tracker, oracle_mod):
     assert len(tr["tracks"]) > 20
 
 
+def test_dense_lattice_fills_tiles(tracker):
+    """The densest patterns of grains: one at every pixel with even x, y and
+    z, and in a single frame one at every even column of every even row
+    (2048 grains in each 8192-pixel run, 64k in the stack)."""
+    from oracle.grains import find_grains
+    for shape in ((6, 64, 1024), (1, 128, 2048)):
+        nz, ny, nx = shape
+        img = np.full(shape, 10, np.uint8)
+        z, y, x = np.meshgrid(np.arange(0, nz, 2), np.arange(0, ny, 2), np.arange(0, nx, 2),
+                              indexing="ij")
+        img[z, y, x] = (100 + (x * 7 + y * 13 + z * 29) % 150).astype(np.uint8)
+        ref, _ = find_grains(img, 60)
+        assert len(ref) == z.size
+        got = tracker.find_grains(img, 60)
+        _say(f"lattice {shape}: {len(ref)} grains")
+        assert np.array_equal(got, ref)
+
+
+def _pixel_centre(pix_w, num, den):
+    """Nearest 0.01 um (halves up) of the weighted mean pixel position times
+    the pitch num/den: the grain coordinate as defined, from exact fractions."""
+    from fractions import Fraction
+    sw = sum(w for _, w in pix_w)
+    f = Fraction(sum(k * w for k, w in pix_w) * num, sw * den) + Fraction(1, 2)
+    return f.numerator // f.denominator
+
+
+def test_largest_stack(emt):
+    """2^31 pixels, the largest stack accepted, on the device: single-pixel
+    grains at the first and last pixels, across a tile boundary inside a row
+    and at a frame boundary come out at their centres, in order."""
+    import torch
+    nz, ny, nx = 128, 1024, 16384
+    num, den = synth_stack.PITCH_NUM, synth_stack.PITCH_DEN
+    _say("largest stack: allocating 2 GiB")
+    dev = torch.zeros((nz, ny, nx), dtype=torch.uint8, device="cuda:0")
+    plant = {(0, 0, 0): 100, (0, 0, 16383): 120, (5, 17, 8191): 150, (5, 17, 8192): 151,
+             (63, 1023, 4096): 130, (64, 0, 0): 140, (127, 1023, 16382): 200,
+             (127, 1023, 16383): 200}
+    for (z, y, x), v in plant.items():
+        dev[z, y, x] = v
+    # expected: every planted pixel but the lower of the pair across the tile
+    # boundary and the later of the equal pair at the end
+    exp = []
+    for (z, y, x) in [(0, 0, 0), (0, 0, 16383), (5, 17, 8192), (63, 1023, 4096), (64, 0, 0),
+                      (127, 1023, 16382)]:
+        block = [((zz, yy, xx), plant.get((zz, yy, xx), 0))
+                 for zz in (z - 1, z, z + 1) for yy in (y - 1, y, y + 1)
+                 for xx in (x - 1, x, x + 1)]
+        block = [(c, w) for c, w in block if w]
+        exp.append([_pixel_centre([(c[2], w) for c, w in block], num[0], den[0]),
+                    _pixel_centre([(c[1], w) for c, w in block], num[1], den[1]),
+                    _pixel_centre([(c[0], w) for c, w in block], num[2], den[2])])
+    out = torch.zeros((16, 3), dtype=torch.int32, device="cuda:0")
+    with emt.Tracker(device=0, flags=emt.EMT_F_DEVICE_PTRS) as t:
+        got = t.find_grains(dev, 60, max_out=16, out=out)
+    _say(f"largest stack: {got.shape[0]} grains")
+    assert got.cpu().numpy().tolist() == exp
+
+
 def test_device_pointers_and_overflow(emt):
     import torch
     from oracle.grains import find_grains

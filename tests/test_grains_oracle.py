@@ -124,6 +124,22 @@ def test_matches_brute_force_on_random_stacks(seed):
     assert xyz.tolist() == [r[0] for r in ref]
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_no_two_grains_are_neighbours(seed):
+    """Two grains are never in each other's 3 x 3 x 3 block (one of them
+    would outrank the other): in particular two pixels next to each other in
+    a row are never both grains, so a run of 2k pixels holds at most k."""
+    rng = np.random.default_rng(50 + seed)
+    img = rng.integers(0, 256, size=(7, 11, 16)).astype(np.uint8)
+    if seed % 2:
+        img = (img // 128 * 128 + 1).astype(np.uint8)   # two levels: ties everywhere
+    _, pix = find_grains(img, 0)
+    assert len(pix) > 0
+    d = np.abs(pix[:, None, :] - pix[None, :, :]).max(axis=2)
+    np.fill_diagonal(d, 2)
+    assert d.min() >= 2
+
+
 def test_recovers_isolated_rendered_spots():
     rng = np.random.default_rng(11)
     dims = (96, 80, 16)
