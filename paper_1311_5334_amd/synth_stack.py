@@ -8,6 +8,12 @@ renders such filtered stacks: every grain of a seeded view (tracks and fog,
 as in the tracking workloads) becomes a 3D Gaussian spot, on a background
 with uniform integer noise, clipped to 8 bits. It holds no step of the
 recognition itself.
+
+It also models the raw camera images the filtering step starts from: the
+same scene seen in bright field (grains dark on a bright background)
+through a camera whose pixels differ in gain, column by column and pixel by
+pixel, together with the per-pixel gain corrections and pedestals a
+calibration would give. It holds no step of the filtering itself.
 """
 from __future__ import annotations
 
@@ -91,3 +97,46 @@ def make_small_stack(seed: int, dims=(64, 48, 12), n_grains: int = 20, threshold
     ext = np.array([nx * pitch_um(0), ny * pitch_um(1), nz * pitch_um(2)])
     centres = rng.uniform(0.0, 1.0, (n_grains, 3)) * ext
     return Stack(render(rng, centres, dims, **kw), centres, threshold, seed)
+
+
+@dataclass
+class RawStack:
+    raw: np.ndarray        # (nz, ny, nx) uint8 camera pulse heights, grains dark
+    gain: np.ndarray       # (ny, nx) uint16 gain corrections, 1/256 units
+    thr: np.ndarray        # (ny, nx) uint8 pedestals
+    scene: np.ndarray      # (nz, ny, nx) uint8 bright-spot scene the raw image shows
+    truth_um: np.ndarray
+    seed: int
+
+
+def camera(rng: np.random.Generator, scene: np.ndarray, bright: int = 235,
+           col_sigma: float = 0.04, pix_sigma: float = 0.01, pedestal: int = 30):
+    """Bright-field raw stack of a bright-spot scene: light = bright - scene,
+    seen through per-pixel camera responses c(x, y) = (1 + column term) (1 +
+    pixel term); the calibration's gain correction is 256 / c and its
+    pedestal `pedestal` plus a small per-pixel spread."""
+    nz, ny, nx = scene.shape
+    col = 1.0 + rng.normal(0.0, col_sigma, nx)
+    pix = 1.0 + rng.normal(0.0, pix_sigma, (ny, nx))
+    c = np.clip(col[None, :] * pix, 0.7, 1.3)
+    light = np.clip(bright - scene.astype(np.float64), 0, 255)
+    raw = np.clip(np.rint(light * c[None, :, :]), 0, 255).astype(np.uint8)
+    gain = np.rint(256.0 / c).astype(np.uint16)
+    thr = (pedestal + rng.integers(0, 4, (ny, nx))).astype(np.uint8)
+    return raw, gain, thr
+
+
+def make_raw_stack(index: int = 0, fog_per_1000_um3: float = 1.0, n_tracks: int = 60,
+                   dims=DIMS) -> RawStack:
+    """The raw camera stack of make_stack's scene, with its calibration."""
+    st = make_stack(index, fog_per_1000_um3, n_tracks, dims)
+    rng = np.random.default_rng(st.seed + 77)
+    raw, gain, thr = camera(rng, st.img)
+    return RawStack(raw, gain, thr, st.img, st.truth_um, st.seed)
+
+
+def make_small_raw_stack(seed: int, dims=(64, 48, 12), n_grains: int = 20, **kw) -> RawStack:
+    st = make_small_stack(seed, dims, n_grains)
+    rng = np.random.default_rng(seed + 77)
+    raw, gain, thr = camera(rng, st.img, **kw)
+    return RawStack(raw, gain, thr, st.img, st.truth_um, seed)
