@@ -175,8 +175,8 @@ int emt_track_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views,
                     emt_view_out *out);
 
 /* Statistics of the last successful emt_track_views. After emt_find_grains
- * with EMT_F_STATS, every field is 0 except ms_total: the device time of the
- * recognition kernels. */
+ * or emt_filter_stack with EMT_F_STATS, every field is 0 except ms_total:
+ * the device time of the recognition or filtering kernels. */
 int emt_last_stats(emt_ctx *ctx, emt_call_stats *stats);
 
 /* Release a context; NULL is ignored. */
@@ -218,6 +218,30 @@ typedef struct {
 int emt_find_grains(emt_ctx *ctx, const uint8_t *stack,
                     const emt_stack_geom *geom, int32_t *xyz_out,
                     uint32_t max_out, uint32_t *n_out);
+
+/*
+ * Image filtering (paper, Sec. 2, image processing paragraph; Fig. 3a, 3b):
+ * the step before grain recognition. The camera's pixels differ in gain, so
+ * each camera pixel (x, y) has its own gain correction and threshold, used
+ * in every frame, and the image is inverted so that grains (dark in the
+ * bright-field image) become bright. Per pixel, on 8-bit pulse heights:
+ * t = min(255, raw * gain / 256 rounded to nearest, halves up);
+ * u = 255 - t; out = u - thr if u > thr, else 0.
+ *
+ * geom: nx, ny, nz as for emt_find_grains (its threshold and pitches are
+ * not used). raw and out: nx*ny*nz bytes (x fastest, frames outermost);
+ * gain: ny*nx uint16 in units of 1/256 (256 = unchanged); thr: ny*nx bytes.
+ * All four are host pointers, or device pointers (each 16-byte aligned,
+ * else EMT_EINVAL) if the context was created with EMT_F_DEVICE_PTRS. raw,
+ * gain and thr are read during the call; out is written before it returns
+ * and may be raw itself (in place; no other overlap). Returns EMT_OK,
+ * EMT_EINVAL (NULL argument), EMT_ERANGE (geometry out of range),
+ * EMT_ENOMEM, EMT_EDEVICE. With
+ * EMT_F_STATS, emt_last_stats reports the kernel's device time in ms_total.
+ */
+int emt_filter_stack(emt_ctx *ctx, const uint8_t *raw,
+                     const emt_stack_geom *geom, const uint16_t *gain,
+                     const uint8_t *thr, uint8_t *out);
 
 /*
  * Serving (paper, Sec. 3: the microscope delivers one view after another at

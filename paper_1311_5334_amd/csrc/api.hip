@@ -962,6 +962,65 @@ static int find_grains_impl(emt_ctx *ctx, const uint8_t *stack, const emt_stack_
     return total > max_out ? EMT_EOVERFLOW : EMT_OK;
 }
 
+static int filter_impl(emt_ctx *ctx, const uint8_t *raw, const emt_stack_geom *g,
+                       const uint16_t *gain, const uint8_t *thr, uint8_t *out) {
+    if (!ctx || !g) return EMT_EINVAL;
+    if (ctx->poisoned) return EMT_EDEVICE;
+    if (g->nx < 4 || (g->nx & 3u) || g->nx > 65536u || g->ny < 1 || g->ny > 65536u ||
+        g->nz < 1 || g->nz > 4096u)
+        return EMT_ERANGE;
+    const unsigned long long plane = (unsigned long long)g->nx * g->ny;
+    const unsigned long long npix = plane * g->nz;
+    if (npix > (1ull << 31)) return EMT_ERANGE;
+    if (!raw || !gain || !thr || !out) return EMT_EINVAL;
+    const bool dev = (ctx->cfg.flags & EMT_F_DEVICE_PTRS) != 0;
+    if (dev && (((uintptr_t)raw | (uintptr_t)gain | (uintptr_t)thr | (uintptr_t)out) & 15u))
+        return EMT_EINVAL;
+    if (hipSetDevice(ctx->cfg.device) != hipSuccess) {
+        ctx->poisoned = true;
+        return EMT_EDEVICE;
+    }
+    int rc;
+    const uint8_t *d_raw = raw, *d_thr = thr;
+    const uint16_t *d_gain = gain;
+    uint8_t *d_out = out;
+    hipStream_t s = ctx->stream;
+    if (!dev) {
+        const size_t bytes = 2 * bytes_of<uint8_t>((size_t)npix) + bytes_of<uint16_t>(plane) +
+                             bytes_of<uint8_t>(plane);
+        if ((rc = arena(ctx, ctx->stack_buf, bytes))) return rc;
+        char *p = (char *)ctx->stack_buf.p;
+        uint8_t *h_raw = carve<uint8_t>(p, (size_t)npix);
+        d_out = carve<uint8_t>(p, (size_t)npix);
+        uint16_t *h_gain = carve<uint16_t>(p, plane);
+        uint8_t *h_thr = carve<uint8_t>(p, plane);
+        HIP_OK(hipMemcpyAsync(h_raw, raw, (size_t)npix, hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(h_gain, gain, 2 * (size_t)plane, hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(h_thr, thr, (size_t)plane, hipMemcpyHostToDevice, s));
+        d_raw = h_raw;
+        d_gain = h_gain;
+        d_thr = h_thr;
+    }
+    const bool stats = (ctx->cfg.flags & EMT_F_STATS) != 0;
+    if (stats) HIP_OK(hipEventRecord(ctx->ev[0], s));
+    if (!launch_filter(d_raw, d_gain, d_thr, d_out, g->nx, g->ny, g->nz, true, s))
+        return EMT_ERANGE;
+    HIP_OK(hipGetLastError());
+    if (stats) HIP_OK(hipEventRecord(ctx->ev[1], s));
+    if (!dev) HIP_OK(hipMemcpyAsync(out, d_out, (size_t)npix, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    ctx->last = emt_call_stats{};
+    if (stats) (void)hipEventElapsedTime(&ctx->last.ms_total, ctx->ev[0], ctx->ev[1]);
+    return EMT_OK;
+}
+
+int emt_filter_stack(emt_ctx *ctx, const uint8_t *raw, const emt_stack_geom *geom,
+                     const uint16_t *gain, const uint8_t *thr, uint8_t *out) {
+    const int rc = filter_impl(ctx, raw, geom, gain, thr, out);
+    (void)hipGetLastError();
+    return rc;
+}
+
 int emt_find_grains(emt_ctx *ctx, const uint8_t *stack, const emt_stack_geom *geom,
                     int32_t *xyz_out, uint32_t max_out, uint32_t *n_out) {
     const int rc = find_grains_impl(ctx, stack, geom, xyz_out, max_out, n_out);

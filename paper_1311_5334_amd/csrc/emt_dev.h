@@ -188,6 +188,12 @@ size_t grain_stage_slots(const StackGeom &G);
 void launch_find_grains(const uint8_t *img, const StackGeom &G, const GrainBufs &b,
                         hipStream_t s);
 
+// Image filtering of an nx x ny x nz stack with per-pixel maps (ny x nx).
+// vec16: every pointer 16-byte aligned (the 16-pixel form is used when the
+// frame size allows it). Returns false if nx * ny is not a multiple of 4.
+bool launch_filter(const uint8_t *raw, const uint16_t *gain, const uint8_t *thr, uint8_t *out,
+                   uint32_t nx, uint32_t ny, uint32_t nz, bool vec16, hipStream_t s);
+
 // Launchers (kernels.hip). All run on `s` and only enqueue work.
 void launch_prepare(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);
 void launch_bin(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s);

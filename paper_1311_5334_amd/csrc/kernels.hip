@@ -1981,6 +1981,104 @@ void launch_find_grains(const uint8_t *img, const StackGeom &G, const GrainBufs 
                                         b.max_out, b.total);
 }
 
+// ---------------------------------------------------------- filtering
+//
+// Image filtering: every camera pixel (x, y) has its own gain correction
+// (unsigned, 1/256 units) and its own threshold, the same in every frame.
+// Per pixel: t = min(255, raw * gain / 256 rounded half up); u = 255 - t
+// (inversion: grains become bright); out = u - thr if u > thr, else 0.
+// A thread owns kPix consecutive pixels of the frame, keeps their gains and
+// thresholds in registers and walks kFilterFrames frames, loading all of
+// them before it computes, so the maps are read once per frame group and
+// raw and filtered pixels stream through once.
+
+namespace {
+
+constexpr uint32_t kFilterFrames = 8;
+
+__device__ __forceinline__ uint32_t filter_word(uint32_t r, uint32_t g01, uint32_t g23,
+                                                uint32_t t) {
+    uint32_t o = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t rb = (r >> (8 * b)) & 0xffu;
+        const uint32_t gb = ((b < 2 ? g01 : g23) >> (16 * (b & 1))) & 0xffffu;
+        const uint32_t tb = (t >> (8 * b)) & 0xffu;
+        const uint32_t tuned = min(255u, (__umul24(rb, gb) + 128u) >> 8);
+        const uint32_t inv = 255u - tuned;
+        o |= (inv > tb ? inv - tb : 0u) << (8 * b);
+    }
+    return o;
+}
+
+template <int kPix>  // pixels a thread owns in each frame: 4 or 16
+__global__ void __launch_bounds__(kBlock) k_filter(const uint8_t *__restrict__ raw,
+                                                   const uint16_t *__restrict__ gain,
+                                                   const uint8_t *__restrict__ thr,
+                                                   uint8_t *__restrict__ out, uint32_t chunks,
+                                                   uint32_t plane, uint32_t nz) {
+    static_assert(kPix == 4 || kPix == 16, "one or four words a frame");
+    constexpr int kW = kPix / 4;  // four-pixel words
+    const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= chunks) return;
+    const uint32_t z0 = blockIdx.y * kFilterFrames;
+    const uint32_t nf = min(kFilterFrames, nz - z0);  // uniform
+    uint32_t g[2 * kW], t[kW];
+    if constexpr (kPix == 16) {
+        const uint4 ga = reinterpret_cast<const uint4 *>(gain)[2 * c];
+        const uint4 gb = reinterpret_cast<const uint4 *>(gain)[2 * c + 1];
+        const uint4 ta = reinterpret_cast<const uint4 *>(thr)[c];
+        g[0] = ga.x; g[1] = ga.y; g[2] = ga.z; g[3] = ga.w;
+        g[4] = gb.x; g[5] = gb.y; g[6] = gb.z; g[7] = gb.w;
+        t[0] = ta.x; t[1] = ta.y; t[2] = ta.z; t[3] = ta.w;
+    } else {
+        const uint2 ga = reinterpret_cast<const uint2 *>(gain)[c];
+        g[0] = ga.x;
+        g[1] = ga.y;
+        t[0] = reinterpret_cast<const uint32_t *>(thr)[c];
+    }
+    uint32_t r[kFilterFrames][kW];
+#pragma unroll
+    for (int f = 0; f < (int)kFilterFrames; ++f) {
+        if ((uint32_t)f >= nf) break;
+        const size_t off = (size_t)(z0 + f) * plane + (size_t)c * kPix;
+        if constexpr (kPix == 16) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(raw + off);
+            r[f][0] = v.x; r[f][1] = v.y; r[f][2] = v.z; r[f][3] = v.w;
+        } else {
+            r[f][0] = *reinterpret_cast<const uint32_t *>(raw + off);
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < (int)kFilterFrames; ++f) {
+        if ((uint32_t)f >= nf) break;
+        uint32_t o[kW];
+#pragma unroll
+        for (int k = 0; k < kW; ++k) o[k] = filter_word(r[f][k], g[2 * k], g[2 * k + 1], t[k]);
+        const size_t off = (size_t)(z0 + f) * plane + (size_t)c * kPix;
+        if constexpr (kPix == 16)
+            *reinterpret_cast<uint4 *>(out + off) = make_uint4(o[0], o[1], o[2], o[3]);
+        else
+            *reinterpret_cast<uint32_t *>(out + off) = o[0];
+    }
+}
+
+}  // namespace
+
+bool launch_filter(const uint8_t *raw, const uint16_t *gain, const uint8_t *thr, uint8_t *out,
+                   uint32_t nx, uint32_t ny, uint32_t nz, bool vec16, hipStream_t s) {
+    const uint32_t plane = nx * ny;
+    if (plane % 4u) return false;
+    if (vec16 && plane % 16u) vec16 = false;
+    const uint32_t pix = vec16 ? 16u : 4u, chunks = plane / pix;
+    const dim3 grid((chunks + kBlock - 1) / kBlock, (nz + kFilterFrames - 1) / kFilterFrames);
+    if (vec16)
+        k_filter<16><<<grid, kBlock, 0, s>>>(raw, gain, thr, out, chunks, plane, nz);
+    else
+        k_filter<4><<<grid, kBlock, 0, s>>>(raw, gain, thr, out, chunks, plane, nz);
+    return true;
+}
+
 namespace {
 
 uint32_t blocks_for(unsigned long long n, uint32_t max_blocks) {

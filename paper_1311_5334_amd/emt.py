@@ -22,7 +22,7 @@ EMT_N_STAGES = len(STAGES)
 EXPORTS = ("emt_default_config", "emt_validate", "emt_create", "emt_track_views",
            "emt_last_stats", "emt_destroy", "emt_strerror", "emt_server_create",
            "emt_server_submit", "emt_server_poll", "emt_server_get_stats",
-           "emt_server_destroy", "emt_find_grains")
+           "emt_server_destroy", "emt_find_grains", "emt_filter_stack")
 # the paper's view (300 x 250 x 50 um) at 1280 x 1024 x 40 pixels: pitches
 # in 0.01 um units as exact fractions
 PAPER_PITCH_NUM, PAPER_PITCH_DEN = (375, 3125, 125), (16, 128, 1)
@@ -143,6 +143,9 @@ def load(path: str = LIB_PATH):
     lib.emt_find_grains.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(EmtStackGeom), C.c_void_p,
                                     C.c_uint32, C.POINTER(C.c_uint32)]
     lib.emt_find_grains.restype = C.c_int
+    lib.emt_filter_stack.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(EmtStackGeom), C.c_void_p,
+                                     C.c_void_p, C.c_void_p]
+    lib.emt_filter_stack.restype = C.c_int
     _lib = lib
     return lib
 
@@ -280,6 +283,40 @@ def emt_find_grains(ctx, stack, threshold: int, device_ptrs: bool = False, max_o
     return buf[:n.value].copy()
 
 
+def emt_filter_stack(ctx, raw, gain, thr, device_ptrs: bool = False, out=None):
+    """Filter a (nz, ny, nx) uint8 stack with (ny, nx) uint16 gains (1/256
+    units) and (ny, nx) uint8 thresholds: numpy arrays, or contiguous CUDA
+    tensors when the context reads device pointers. Returns the filtered
+    stack (numpy, or ``out`` / a new CUDA tensor)."""
+    lib = load()
+    nz, ny, nx = (int(v) for v in raw.shape)
+    g = stack_geom(raw.shape, 0)
+    if tuple(gain.shape) != (ny, nx) or tuple(thr.shape) != (ny, nx):
+        raise ValueError("gain and thr must be (ny, nx) maps")
+    if device_ptrs:
+        import torch
+        for t, size in ((raw, 1), (gain, 2), (thr, 1)):
+            if not (t.is_cuda and t.is_contiguous() and t.element_size() == size):
+                raise TypeError("device stacks and maps must be contiguous CUDA tensors "
+                                "(8-bit stack and thresholds, 16-bit gains)")
+        if out is None:
+            out = torch.empty_like(raw)
+        rc = lib.emt_filter_stack(ctx, raw.data_ptr(), C.byref(g), gain.data_ptr(),
+                                  thr.data_ptr(), out.data_ptr())
+        if rc != EMT_OK:
+            raise EmtError(rc, "emt_filter_stack")
+        return out
+    a = np.ascontiguousarray(np.asarray(raw, dtype=np.uint8))
+    gm = np.ascontiguousarray(np.asarray(gain, dtype=np.uint16))
+    tm = np.ascontiguousarray(np.asarray(thr, dtype=np.uint8))
+    res = np.empty_like(a) if out is None else out
+    rc = lib.emt_filter_stack(ctx, a.ctypes.data, C.byref(g), gm.ctypes.data, tm.ctypes.data,
+                              res.ctypes.data)
+    if rc != EMT_OK:
+        raise EmtError(rc, "emt_filter_stack")
+    return res
+
+
 def emt_last_stats(ctx) -> dict:
     st = EmtCallStats()
     rc = load().emt_last_stats(ctx, C.byref(st))
@@ -311,6 +348,9 @@ class Tracker:
 
     def find_grains(self, stack, threshold: int, **kw):
         return emt_find_grains(self.ctx, stack, threshold, self.device_ptrs, **kw)
+
+    def filter_stack(self, raw, gain, thr, **kw):
+        return emt_filter_stack(self.ctx, raw, gain, thr, self.device_ptrs, **kw)
 
     def close(self):
         if self.ctx is not None:

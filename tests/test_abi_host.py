@@ -175,3 +175,10 @@ def test_find_grains_rejects_null_without_device(emt):
     g = emt.stack_geom((4, 8, 16), 60)
     assert lib.emt_find_grains(None, None, C.byref(g), None, 0, C.byref(n)) == -1
     assert lib.emt_find_grains(None, None, None, None, 0, None) == -1
+
+
+def test_filter_stack_rejects_null_without_device(emt):
+    lib = emt.load()
+    g = emt.stack_geom((4, 8, 16), 0)
+    assert lib.emt_filter_stack(None, None, C.byref(g), None, None, None) == -1
+    assert lib.emt_filter_stack(None, None, None, None, None, None) == -1
