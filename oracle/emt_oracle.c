@@ -113,9 +113,16 @@ static void grid_free(grid_t *G) {
 
 /* The cylinder predicate of step (2): with d = g_j - g_i and w = g_k - g_i,
  * grain k lies within r of the (infinite) line iff |w x d|^2 <= r^2 |d|^2.
- * The radius is inclusive. Exact in int64 under the span and R limits. */
+ * The radius is inclusive. Exact in int64 under the span and R limits.
+ *
+ * Acceptance variant (finite cylinder), ext >= 0: grain k must also project
+ * onto the line no further than ext beyond either seed grain, i.e. with
+ * t = w.d, -ext |d| <= t <= |d|^2 + ext |d|. Both sides are compared
+ * squared where they are negative: t >= -ext |d| holds if t >= 0, else iff
+ * t^2 <= ext^2 |d|^2; likewise for t - |d|^2 <= ext |d|. (|t| < 2^31 and
+ * ext^2 |d|^2 < 2^59, so int64 is exact.) */
 static int on_line(const int32_t *xyz, uint32_t i, const int64_t d[3],
-                   int64_t r2D, uint32_t k) {
+                   int64_t r2D, int64_t ext, uint32_t k) {
     const int32_t *gi = xyz + 3 * (size_t)i, *gk = xyz + 3 * (size_t)k;
     int64_t w0 = (int64_t)gk[0] - gi[0];
     int64_t w1 = (int64_t)gk[1] - gi[1];
@@ -123,7 +130,45 @@ static int on_line(const int32_t *xyz, uint32_t i, const int64_t d[3],
     int64_t c0 = w1 * d[2] - w2 * d[1];
     int64_t c1 = w2 * d[0] - w0 * d[2];
     int64_t c2 = w0 * d[1] - w1 * d[0];
-    return c0 * c0 + c1 * c1 + c2 * c2 <= r2D;
+    if (c0 * c0 + c1 * c1 + c2 * c2 > r2D) return 0;
+    if (ext < 0) return 1;
+    int64_t D = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    int64_t t = w0 * d[0] + w1 * d[1] + w2 * d[2];
+    int64_t e2D = ext * ext * D;
+    if (t < 0 && t * t > e2D) return 0;
+    if (t > D && (t - D) * (t - D) > e2D) return 0;
+    return 1;
+}
+
+/* Acceptance variant (grain-count threshold rising with the angle; paper
+ * Sec. 4: a cut on the number of grains along a line in the plane of grain
+ * count against track angle, Fig. 9c). For seed direction d, with
+ * tan(theta) = sqrt(d_x^2 + d_y^2) / |d_z| and b = thr_num / thr_den, the
+ * threshold is the smallest integer m >= n_min with m - n_min >= b tan(theta),
+ * capped at thr_max (if set). Tested exactly, squared in 128-bit integers:
+ * ((m - n_min) |d_z| thr_den)^2 >= thr_num^2 (d_x^2 + d_y^2); the smallest
+ * such m is found by bisection (the test is monotone in m). A seed with
+ * d_z = 0 gets the cap (no cap: no count suffices). */
+static uint32_t seed_threshold(const int64_t d[3], const emto_params *p) {
+    const uint32_t n_min = (uint32_t)p->min_grains;
+    if (p->thr_num == 0) return n_min;
+    const uint32_t cap = p->thr_max > 0 ? (uint32_t)p->thr_max : UINT32_MAX;
+    const int64_t adz = d[2] < 0 ? -d[2] : d[2];
+    if (adz == 0) return cap;
+    const unsigned __int128 rhs = (unsigned __int128)((int64_t)p->thr_num * p->thr_num) *
+                                  (unsigned __int128)(d[0] * d[0] + d[1] * d[1]);
+    /* m - n_min never needs more than thr_num * |d| < 2^24 */
+    uint64_t lo = 0, hi = (uint64_t)1 << 24;
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) / 2;
+        unsigned __int128 l = (unsigned __int128)(mid * (uint64_t)adz * (uint64_t)p->thr_den);
+        if (l * l >= rhs)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    uint64_t m = (uint64_t)n_min + lo;
+    return m < cap ? (uint32_t)m : cap;
 }
 
 /* Count (and optionally list) the grains on the line of seed (i, j).
@@ -141,8 +186,8 @@ static int on_line(const int32_t *xyz, uint32_t i, const int64_t d[3],
  * Those cells are visited and the exact predicate decides; the double
  * arithmetic here only chooses cells and gets a 1-unit safety margin. */
 static uint32_t count_seed(const grid_t *G, const int32_t *xyz, uint32_t n,
-                           uint32_t i, uint32_t j, int64_t r, int scan_all,
-                           uint64_t *tests, uint32_t *list) {
+                           uint32_t i, uint32_t j, int64_t r, int64_t ext,
+                           int scan_all, uint64_t *tests, uint32_t *list) {
     const int32_t *gi = xyz + 3 * (size_t)i, *gj = xyz + 3 * (size_t)j;
     int64_t d[3] = {(int64_t)gj[0] - gi[0], (int64_t)gj[1] - gi[1],
                     (int64_t)gj[2] - gi[2]};
@@ -151,7 +196,7 @@ static uint32_t count_seed(const grid_t *G, const int32_t *xyz, uint32_t n,
     uint32_t cnt = 0;
     if (scan_all || !G) {
         for (uint32_t k = 0; k < n; k++) {
-            if (on_line(xyz, i, d, r2D, k)) {
+            if (on_line(xyz, i, d, r2D, ext, k)) {
                 if (list) list[cnt] = k;
                 cnt++;
             }
@@ -199,7 +244,7 @@ static uint32_t count_seed(const grid_t *G, const int32_t *xyz, uint32_t n,
                 for (uint32_t t = G->start[cid]; t < G->start[cid + 1]; t++) {
                     uint32_t k = G->item[t];
                     if (tests) (*tests)++;
-                    if (on_line(xyz, i, d, r2D, k)) {
+                    if (on_line(xyz, i, d, r2D, ext, k)) {
                         if (list) list[cnt] = k;
                         cnt++;
                     }
@@ -215,7 +260,7 @@ uint32_t emto_count_seed(const int32_t *xyz, uint32_t n, uint32_t i,
     if (!xyz || i >= n || j >= n) return 0;
     const int32_t *gi = xyz + 3 * (size_t)i, *gj = xyz + 3 * (size_t)j;
     if (gi[0] == gj[0] && gi[1] == gj[1] && gi[2] == gj[2]) return 0;
-    return count_seed(NULL, xyz, n, i, j, r, 1, NULL, NULL);
+    return count_seed(NULL, xyz, n, i, j, r, -1, 1, NULL, NULL);
 }
 
 /* Priority of step (4): the paper fixes no order for the exclusive
@@ -346,6 +391,10 @@ int emto_track_view(const int32_t *xyz, uint32_t n, const emto_params *p,
         p->tol_radius >= p->seed_dist || p->min_grains < 2 ||
         (uint32_t)p->min_grains >= N_MAX)
         return EMTO_ERANGE;
+    if (p->cyl_ext < -1 || p->cyl_ext > SPAN_MAX || p->thr_num < 0 || p->thr_num > 1024 ||
+        p->thr_den < 1 || p->thr_den > 1024 || p->thr_max < 0 ||
+        (p->thr_max > 0 && (p->thr_max < p->min_grains || (uint32_t)p->thr_max >= N_MAX)))
+        return EMTO_ERANGE;
     if (n >= N_MAX) return EMTO_ERANGE;
     if (n) {
         for (int m = 0; m < 3; m++) {
@@ -403,9 +452,10 @@ int emto_track_view(const int32_t *xyz, uint32_t n, const emto_params *p,
                         int64_t D = d0 * d0 + d1 * d1 + d2 * d2;
                         if (D <= 0 || D >= R2) continue;
                         nseeds++;
-                        uint32_t cnt = count_seed(&G, xyz, n, i, j, r,
+                        uint32_t cnt = count_seed(&G, xyz, n, i, j, r, p->cyl_ext,
                                                   p->scan_all, &ntests, NULL);
-                        if (cnt >= (uint32_t)p->min_grains) {
+                        const int64_t dd[3] = {d0, d1, d2};
+                        if (cnt >= seed_threshold(dd, p)) {
                             if (ncand == cap) {
                                 cap *= 2;
                                 emto_cand *nc = (emto_cand *)realloc(
@@ -446,12 +496,17 @@ int emto_track_view(const int32_t *xyz, uint32_t n, const emto_params *p,
     uint32_t ntr = 0, ngr = 0;
     for (uint32_t s = 0; s < ncand; s++) {
         uint32_t i = cand[s].i, j = cand[s].j;
-        uint32_t cnt = count_seed(&G, xyz, n, i, j, r, p->scan_all, NULL,
-                                  members);
+        uint32_t cnt = count_seed(&G, xyz, n, i, j, r, p->cyl_ext, p->scan_all,
+                                  NULL, members);
         uint32_t m = 0;
         for (uint32_t q = 0; q < cnt; q++)
             if (!used[members[q]]) members[m++] = members[q];
-        if (m < (uint32_t)p->min_grains) continue;
+        {
+            const int32_t *si = xyz + 3 * (size_t)i, *sj = xyz + 3 * (size_t)j;
+            const int64_t sd[3] = {(int64_t)sj[0] - si[0], (int64_t)sj[1] - si[1],
+                                   (int64_t)sj[2] - si[2]};
+            if (m < seed_threshold(sd, p)) continue;
+        }
         for (uint32_t q = 0; q < m; q++) used[members[q]] = 1;
         /* Track record: grains ordered along the seed direction by
          * t = (g_k - g_i).d, ties by input index. */

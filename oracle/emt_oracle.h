@@ -10,7 +10,9 @@
  * Sec. 3 footnote):
  *   seeds      every grain pair closer than R, any direction (Fig. 4a)
  *   count      grains within r of the infinite line through the pair (Fig. 4b)
- *   threshold  keep seeds with at least n_min grains
+ *              (variant: of a finite cylinder around the pair)
+ *   threshold  keep seeds with at least n_min grains (variant: a threshold
+ *              rising with the seed's angle to the z axis, Sec. 4, Fig. 9c)
  *   associate  each grain used by one track only, then the threshold again
  *   fit        least-squares direction of each accepted track (FP64)
  *
@@ -40,6 +42,12 @@ typedef struct {
     int32_t scan_all;   /* 1: count every seed over all N grains (the definition);
                            0: visit only the hash cells the cylinder can reach     */
     int32_t cell[3];    /* hash cell edge per axis in units (acceleration only)    */
+    int32_t thr_num;    /* acceptance variant: a seed needs n_min + ceil(b tan th)  */
+    int32_t thr_den;    /*   grains, b = thr_num / thr_den (thr_num 0: n_min)       */
+    int32_t thr_max;    /*   that threshold capped at thr_max (0: no cap)          */
+    int64_t cyl_ext;    /* -1: infinite line; >= 0: finite cylinder, grains whose
+                           projection lies at most cyl_ext units beyond a seed
+                           grain along the line                                   */
 } emto_params;
 
 typedef struct {

@@ -31,7 +31,8 @@ def build(force: bool = False) -> str:
 class _Params(C.Structure):
     _fields_ = [("seed_dist", C.c_int64), ("tol_radius", C.c_int64),
                 ("min_grains", C.c_int32), ("scan_all", C.c_int32),
-                ("cell", C.c_int32 * 3)]
+                ("cell", C.c_int32 * 3), ("thr_num", C.c_int32), ("thr_den", C.c_int32),
+                ("thr_max", C.c_int32), ("cyl_ext", C.c_int64)]
 
 
 class _Cand(C.Structure):
@@ -92,10 +93,16 @@ class OracleError(RuntimeError):
 
 
 def track_view(xyz, R: int = 2500, r: int = 50, n_min: int = 8,
-               scan_all: bool = False, cell=(750, 750, 170)) -> OracleResult:
+               scan_all: bool = False, cell=(750, 750, 170), cyl_ext: int = -1,
+               thr_slope=(0, 1), thr_max: int = 0) -> OracleResult:
+    """Track one view. Acceptance variants: cyl_ext >= 0 counts only grains
+    projecting at most cyl_ext units beyond a seed grain (finite cylinder);
+    thr_slope = (num, den) raises the grain-count threshold to
+    n_min + ceil(num/den tan(theta)) of the seed, capped at thr_max if set."""
     lib = _load()
     a = np.ascontiguousarray(np.asarray(xyz, dtype=np.int32).reshape(-1, 3))
-    p = _Params(R, r, n_min, 1 if scan_all else 0, (C.c_int32 * 3)(*cell))
+    p = _Params(R, r, n_min, 1 if scan_all else 0, (C.c_int32 * 3)(*cell),
+                int(thr_slope[0]), int(thr_slope[1]), int(thr_max), int(cyl_ext))
     res = _Result()
     rc = lib.emto_track_view(a.ctypes.data if a.size else None, a.shape[0],
                              C.byref(p), C.byref(res))
