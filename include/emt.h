@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define EMT_ABI_VERSION 1u
+#define EMT_ABI_VERSION 2u
 
 /* Return codes. */
 #define EMT_OK 0
@@ -74,6 +74,21 @@ extern "C" {
  *   flags       EMT_F_* bits.
  *   hbm_budget  device bytes the context may hold (0 = 80 % of free memory).
  *   stream      hipStream_t to run on, or NULL for a library-owned stream.
+ * Acceptance variants (defaults: off):
+ *   cyl_ext     -1 (default): grains are counted along the infinite line
+ *               through the seed. 0 .. 2^18: a finite cylinder, counting
+ *               only grains whose projection on the line lies at most
+ *               cyl_ext units beyond either seed grain, i.e. with
+ *               t = (g_k - g_i).(g_j - g_i): -cyl_ext |d| <= t <=
+ *               |d|^2 + cyl_ext |d| (exact).
+ *   thr_slope   {num, den}: a seed needs n_min + ceil(num/den tan(theta))
+ *               grains, theta the angle of the seed pair to the z axis
+ *               (tan = sqrt(dx^2 + dy^2) / |dz|), in both threshold steps;
+ *               after the paper's grain-count cut against track angle
+ *               (Sec. 4, Fig. 9c). num 0 (default): the threshold is n_min.
+ *               num 0..1024, den 1..1024.
+ *   thr_max     cap of that threshold (0: none; else n_min..2^20-1); a seed
+ *               with dz = 0 needs the cap (no cap: it is never a track).
  */
 typedef struct {
     uint32_t abi_version;
@@ -85,6 +100,9 @@ typedef struct {
     uint32_t flags;
     uint64_t hbm_budget;
     void *stream;
+    int32_t cyl_ext;
+    int32_t thr_slope[2];
+    int32_t thr_max;
 } emt_config;
 
 /* One view in. xyz: n_grains x 3 int32 (x, y, z interleaved), owned by the

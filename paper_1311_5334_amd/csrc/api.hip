@@ -110,6 +110,13 @@ int check_config(const emt_config *c) {
     if (c->tol_radius < 0 || c->tol_radius >= c->seed_dist) return EMT_ERANGE;
     if (c->min_grains < 2 || (uint32_t)c->min_grains >= kNMax) return EMT_ERANGE;
     if (c->cell[0] > kSpanMax || c->cell[1] > kSpanMax || c->cell[2] > kSpanMax) return EMT_ERANGE;
+    if (c->cyl_ext < -1 || c->cyl_ext > kSpanMax) return EMT_ERANGE;
+    if (c->thr_slope[0] < 0 || c->thr_slope[0] > 1024 || c->thr_slope[1] < 1 ||
+        c->thr_slope[1] > 1024)
+        return EMT_ERANGE;
+    if (c->thr_max < 0 ||
+        (c->thr_max > 0 && (c->thr_max < c->min_grains || (uint32_t)c->thr_max >= kNMax)))
+        return EMT_ERANGE;
     return EMT_OK;
 }
 
@@ -238,7 +245,7 @@ size_t seed_bytes(size_t n) {
 }
 size_t cand_bytes(size_t n) {
     return bytes_of<Cand>(n) + bytes_of<unsigned long long>(n) + 4 * bytes_of<uint32_t>(n + 1) +
-           6 * bytes_of<uint32_t>(n) + bytes_of<uint8_t>(n) + bytes_of<emt_track>(n);
+           7 * bytes_of<uint32_t>(n) + bytes_of<uint8_t>(n) + bytes_of<emt_track>(n);
 }
 size_t mem_bytes(size_t n) {
     return 3 * bytes_of<uint32_t>(n) + bytes_of<uint8_t>(n) + bytes_of<long long>(n);
@@ -296,6 +303,7 @@ int ensure(emt_ctx *ctx, Caps &c) {
         d.cand = carve<Cand>(p, n);
         d.key = carve<unsigned long long>(p, n);
         d.cand_n = carve<uint32_t>(p, n + 1);
+        d.cand_thr = carve<uint32_t>(p, n);
         d.mem_off = carve<uint32_t>(p, n + 1);
         d.tg_n = carve<uint32_t>(p, n + 1);
         d.tg_off = carve<uint32_t>(p, n + 1);
@@ -605,6 +613,10 @@ void emt_default_config(emt_config *cfg) {
     cfg->flags = 0;
     cfg->hbm_budget = 0;
     cfg->stream = nullptr;
+    cfg->cyl_ext = -1;
+    cfg->thr_slope[0] = 0;
+    cfg->thr_slope[1] = 1;
+    cfg->thr_max = 0;
 }
 
 int emt_validate(const emt_config *cfg, const emt_view_in *views, uint32_t n_views) {
@@ -642,6 +654,10 @@ int emt_create(const emt_config *cfg, emt_ctx **out) {
     ctx->P.R = cfg->seed_dist;
     ctx->P.r = cfg->tol_radius;
     ctx->P.n_min = cfg->min_grains;
+    ctx->P.cyl_ext = cfg->cyl_ext;
+    ctx->P.thr_num = cfg->thr_slope[0];
+    ctx->P.thr_den = cfg->thr_slope[1];
+    ctx->P.thr_max = cfg->thr_max;
     // cell edges: per view from the tuned density table when none is given
     ctx->P.auto_cells = (cfg->cell[0] || cfg->cell[1] || cfg->cell[2]) ? 0 : 1;
     for (int m = 0; m < 3; ++m) ctx->P.cell_req[m] = cfg->cell[m] ? cfg->cell[m] : kDefaultCell[m];

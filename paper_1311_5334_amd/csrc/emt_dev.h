@@ -49,6 +49,11 @@ constexpr double kCellEdge0 = 0.75;
 
 struct Params {
     int32_t R, r, n_min, pad0;
+    // acceptance variants: cyl_ext < 0 the infinite line, else a finite
+    // cylinder reaching cyl_ext units beyond each seed grain; thr_num > 0
+    // a threshold n_min + ceil(thr_num / thr_den tan(theta)), capped at
+    // thr_max when thr_max > 0
+    int32_t cyl_ext, thr_num, thr_den, thr_max;
     int32_t cell_req[3];  // fixed cell edges, used when auto_cells == 0
     uint32_t flags;
     int32_t auto_cells;   // 1: per view from cell_tab by density
@@ -120,6 +125,7 @@ struct DevPtrs {
     Cand *cand;           // cand_cap
     unsigned long long *key;  // cand_cap
     uint32_t *cand_n;     // cand_cap + 1
+    uint32_t *cand_thr;   // cand_cap: grain-count threshold of each candidate
     uint32_t *mem_off;    // cand_cap + 1
     uint32_t *members;    // mem_cap
     uint8_t *taken;       // mem_cap

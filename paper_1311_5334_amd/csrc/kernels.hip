@@ -555,6 +555,49 @@ __device__ __forceinline__ bool cyl_hit(int4 h, int4 A, int4 B, int tol_r) {
     return cc <= (long long)tol_r * tol_r * D;
 }
 
+// Acceptance variants.
+//
+// Finite cylinder: grain k also needs t = g_k.d in [lo, hi], lo = g_i.d - F,
+// hi = g_i.d + |d|^2 + F, F = floor(cyl_ext |d|) = isqrt(cyl_ext^2 |d|^2):
+// t is an integer, so t - g_i.d >= -cyl_ext |d| iff t >= g_i.d - F, and
+// likewise above. Coordinates are in [0, 2^18] and |d| < 2^12, so |t| < 2^31
+// and the 24-bit products are exact; the bounds are clamped to int32.
+__device__ __forceinline__ int2 axial_bounds(int4 gi, int dx, int dy, int dz, int ext) {
+    const long long D = (long long)dx * dx + (long long)dy * dy + (long long)dz * dz;
+    const long long e2D = (long long)ext * ext * D;  // < 2^59
+    long long F = (long long)sqrt((double)e2D);
+    while (F > 0 && F * F > e2D) --F;
+    while ((F + 1) * (F + 1) <= e2D) ++F;
+    const long long gd = (long long)gi.x * dx + (long long)gi.y * dy + (long long)gi.z * dz;
+    const long long lo = gd - F, hi = gd + D + F;
+    return make_int2((int)max(lo, -2147483647ll - 1), (int)min(hi, 2147483647ll));
+}
+
+__device__ __forceinline__ bool axial_ok(int4 h, int4 A, int2 b) {
+    const int t = __mul24(h.x, A.x) + __mul24(h.y, A.y) + __mul24(h.z, A.z);
+    return t >= b.x && t <= b.y;
+}
+
+// Grain-count threshold of a seed with direction d: n_min + ceil(b tan(theta)),
+// b = thr_num / thr_den, tan(theta) = sqrt(dx^2 + dy^2) / |dz|, capped at
+// thr_max when set; dz = 0 needs the cap (no cap: unreachable). The ceiling
+// m = ceil(sqrt(Q) / K), Q = thr_num^2 (dx^2 + dy^2), K = thr_den |dz|, is the
+// smallest m >= 0 with (m K)^2 >= Q: a double estimate, corrected with exact
+// integer squares (m K < 2^23).
+__device__ __forceinline__ uint32_t seed_threshold(int dx, int dy, int dz, const Params &P) {
+    if (P.thr_num == 0) return (uint32_t)P.n_min;
+    const uint32_t cap = P.thr_max > 0 ? (uint32_t)P.thr_max : 0xffffffffu;
+    const long long K = (long long)P.thr_den * (dz < 0 ? -dz : dz);
+    if (K == 0) return cap;
+    const long long Q =
+        (long long)P.thr_num * P.thr_num * ((long long)dx * dx + (long long)dy * dy);
+    long long m = (long long)ceil(sqrt((double)Q) / (double)K);
+    while (m > 0 && (m - 1) * K * (m - 1) * K >= Q) --m;
+    while (m * K * m * K < Q) ++m;
+    const long long t = (long long)P.n_min + m;
+    return t < (long long)cap ? (uint32_t)t : cap;
+}
+
 // Next grab of items for the calling wave: its own
 // XCD's range first, then the others. grab[16 x] is range x's offset
 // counter. Grabs are a quarter of a range's remainder per wave of the XCD,
@@ -688,9 +731,11 @@ static_assert(kSlotCap >= 2 * 64 * kLaneCap && kSlotCap <= 4096, "member queue s
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaskWords = kSlotCap / 64;
 
+template <bool kFinite>
 struct QueueLds {
     int4 pa[64];  // dx, dy, dz, tlo
     int4 pb[64];  // ex, ey, ez, thi
+    int2 pc[kFinite ? 64 : 1];  // finite cylinder: bounds of g_k.d
     uint32_t cnt[64];
     uint32_t out_off[64];
     uint32_t ncap[64];
@@ -730,7 +775,8 @@ __device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t x) {
     return v;
 }
 
-__device__ __forceinline__ void flush_queue(QueueLds &Q, uint32_t qn, int tol_r, const int4 *__restrict__ sg,
+template <bool kFinite>
+__device__ __forceinline__ void flush_queue(QueueLds<kFinite> &Q, uint32_t qn, int tol_r, const int4 *__restrict__ sg,
                                             uint32_t *__restrict__ members, int lane) {
     wave_lds_sync();
     const uint32_t nw = (qn + 63) >> 6;
@@ -751,7 +797,8 @@ __device__ __forceinline__ void flush_queue(QueueLds &Q, uint32_t qn, int tol_r,
             const uint32_t kk = Q.run_k[r] + (s - (tag & 0xffffu));
             const uint32_t sl = tag >> 16;
             const int4 h = sg[kk];
-            if (cyl_hit(h, Q.pa[sl], Q.pb[sl], tol_r)) {
+            if (cyl_hit(h, Q.pa[sl], Q.pb[sl], tol_r) &&
+                (!kFinite || axial_ok(h, Q.pa[sl], Q.pc[sl]))) {
                 const uint32_t pos = atomicAdd(&Q.cnt[sl], 1u);
                 if (pos < Q.ncap[sl]) members[Q.out_off[sl] + pos] = kk;
             }
@@ -762,13 +809,13 @@ __device__ __forceinline__ void flush_queue(QueueLds &Q, uint32_t qn, int tol_r,
     wave_lds_sync();
 }
 
-template <int kPer>
+template <int kPer, bool kFinite>
 __global__ void __launch_bounds__(kBlock) k_members(DevPtrs d, Caps c, Params P) {
-    __shared__ QueueLds sQ[kWaves];
+    __shared__ QueueLds<kFinite> sQ[kWaves];
     const int lane = lane_id();
     const int slot = lane / kPer, sub = lane % kPer;
     constexpr int kItems = 64 / kPer;
-    QueueLds &Q = sQ[threadIdx.x >> 6];
+    QueueLds<kFinite> &Q = sQ[threadIdx.x >> 6];
     const uint32_t nc = d.cnt->n_cand;
     const unsigned long long n_items = d.cnt->err ? 0ull : (nc < c.cand_cap ? nc : c.cand_cap);
     if (lane < kMaskWords) Q.mask[lane] = 0ull;
@@ -793,6 +840,7 @@ __global__ void __launch_bounds__(kBlock) k_members(DevPtrs d, Caps c, Params P)
         if (sub == 0) {
             Q.pa[slot] = make_int4(dx, dy, dz, __float_as_int(L.tlo));
             Q.pb[slot] = make_int4((int)L.ex, (int)L.ey, (int)L.ez, __float_as_int(L.thi));
+            if constexpr (kFinite) Q.pc[slot] = axial_bounds(gi, dx, dy, dz, P.cyl_ext);
             Q.cnt[slot] = 0;
             Q.out_off[slot] = off;
             Q.ncap[slot] = ncap;
@@ -895,16 +943,19 @@ static_assert(64 * kFetch <= kCountRunCap, "a step's runs must fit the run queue
 static_assert(kCountSlotCap >= 64 * kCountLaneCap, "a step's tests must fit the slot queue");
 static_assert(kCountMaskWords <= 64, "one mask word per lane");
 
+template <bool kFinite>
 struct CountLds {
     int4 pa[kCountSlots];
     int4 pb[kCountSlots];
+    int2 pc[kFinite ? kCountSlots : 1];  // finite cylinder: bounds of g_k.d
     uint32_t cnt[kCountSlots];
     unsigned long long mask[kCountMaskWords];
     uint32_t before[kCountMaskWords];
     uint2 run[kCountRunCap];  // first grain, first queue slot | seed slot << 16
 };
 
-__device__ __forceinline__ void count_flush(CountLds &Q, uint32_t qn, int tol_r, const int4 *__restrict__ sg,
+template <bool kFinite>
+__device__ __forceinline__ void count_flush(CountLds<kFinite> &Q, uint32_t qn, int tol_r, const int4 *__restrict__ sg,
                                             int lane) {
     wave_lds_sync();
     const uint32_t nw = (qn + 63) >> 6;
@@ -925,7 +976,9 @@ __device__ __forceinline__ void count_flush(CountLds &Q, uint32_t qn, int tol_r,
             const uint32_t kk = rec.x + (s - (tag & 0xffffu));
             const uint32_t sl = tag >> 16;
             const int4 h = sg[kk];
-            if (cyl_hit(h, Q.pa[sl], Q.pb[sl], tol_r)) atomicAdd(&Q.cnt[sl], 1u);
+            if (cyl_hit(h, Q.pa[sl], Q.pb[sl], tol_r) &&
+                (!kFinite || axial_ok(h, Q.pa[sl], Q.pc[sl])))
+                atomicAdd(&Q.cnt[sl], 1u);
         }
     }
     wave_lds_sync();
@@ -933,10 +986,11 @@ __device__ __forceinline__ void count_flush(CountLds &Q, uint32_t qn, int tol_r,
     wave_lds_sync();
 }
 
+template <bool kFinite>
 __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
-    __shared__ CountLds sQ[kWaves];
+    __shared__ CountLds<kFinite> sQ[kWaves];
     const int lane = lane_id();
-    CountLds &Q = sQ[threadIdx.x >> 6];
+    CountLds<kFinite> &Q = sQ[threadIdx.x >> 6];
     const unsigned long long ns = d.cnt->n_seeds;
     const uint32_t n_items = (uint32_t)(ns < c.seed_cap ? ns : c.seed_cap);
     if (lane < kCountMaskWords) Q.mask[lane] = 0ull;
@@ -962,6 +1016,7 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
     bool have = false;
     bool pend0 = false, pend1 = false;  // slot closed, count not yet written
     uint32_t idx0 = 0, idx1 = 0;        // seed index held by each slot
+    uint32_t th0 = 0, th1 = 0;          // grain-count threshold of each slot's seed
     int cur = lane;
     Pencil W;
     W.live = false;
@@ -974,13 +1029,13 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
         if (pend0) {
             const uint32_t n = Q.cnt[lane];
             hits += n;
-            d.seed_n[idx0] = n >= (uint32_t)P.n_min ? n : 0u;
+            d.seed_n[idx0] = n >= th0 ? n : 0u;
             pend0 = false;
         }
         if (pend1) {
             const uint32_t n = Q.cnt[lane + 64];
             hits += n;
-            d.seed_n[idx1] = n >= (uint32_t)P.n_min ? n : 0u;
+            d.seed_n[idx1] = n >= th1 ? n : 0u;
             pend1 = false;
         }
         wave_lds_sync();
@@ -1007,11 +1062,19 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
             if (take) {
                 const uint32_t idx = next + rank;
                 cur = pend0 ? lane + 64 : lane;
-                if (cur == lane) idx0 = idx; else idx1 = idx;
                 const uint2 pq = d.seeds[idx];
                 const uint32_t v = d.view_of[pq.x];
                 const int4 gi = d.sg[pq.x], gj = d.sg[pq.y];
                 const int dx = gj.x - gi.x, dy = gj.y - gi.y, dz = gj.z - gi.z;
+                const uint32_t th = seed_threshold(dx, dy, dz, P);
+                if (cur == lane) {
+                    idx0 = idx;
+                    th0 = th;
+                } else {
+                    idx1 = idx;
+                    th1 = th;
+                }
+                if constexpr (kFinite) Q.pc[cur] = axial_bounds(gi, dx, dy, dz, P.cyl_ext);
                 LineTest L;
                 L.init(gi, dx, dy, dz, P.r);
                 Q.pa[cur] = make_int4(dx, dy, dz, __float_as_int(L.tlo));
@@ -1100,7 +1163,7 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
 // counts (for the member offsets); and the seeds and candidates of each
 // view, from the offsets (views are contiguous in anchor order, so in seed
 // and in candidate order too).
-__global__ void __launch_bounds__(kBlock) k_cand_scatter(DevPtrs d, Caps c) {
+__global__ void __launch_bounds__(kBlock) k_cand_scatter(DevPtrs d, Caps c, Params P) {
     const uint32_t ns = min(d.cnt->n_seeds, (uint32_t)c.seed_cap);
     for (uint32_t v = grid_tid(); v < d.desc->n_views; v += grid_threads()) {
         const uint32_t g0 = d.grids[v].grain_off, g1 = g0 + d.grids[v].n;
@@ -1121,8 +1184,16 @@ __global__ void __launch_bounds__(kBlock) k_cand_scatter(DevPtrs d, Caps c) {
         cd.v = d.view_of[pq.x];
         d.cand[pos] = cd;
         d.cand_n[pos] = n;
-        d.key[pos] = cand_key(n, (uint32_t)d.sg[pq.x].w, (uint32_t)d.sg[pq.y].w);
+        const int4 gi = d.sg[pq.x], gj = d.sg[pq.y];
+        if (P.thr_num) d.cand_thr[pos] = seed_threshold(gj.x - gi.x, gj.y - gi.y, gj.z - gi.z, P);
+        d.key[pos] = cand_key(n, (uint32_t)gi.w, (uint32_t)gj.w);
     }
+}
+
+// The threshold a candidate's unused grains must reach: n_min, or its own
+// angle-dependent threshold when that variant is on.
+__device__ __forceinline__ uint32_t cand_min(const DevPtrs &d, const Params &P, uint32_t ci) {
+    return P.thr_num ? d.cand_thr[ci] : (uint32_t)P.n_min;
 }
 
 // ----------------------------------------------------------------- merge
@@ -1240,7 +1311,7 @@ __global__ void __launch_bounds__(kBlock) k_round(DevPtrs d, Params P, int round
                 for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup)
                     unused += d.used[d.members[e]] ? 0u : 1u;
                 unused = group_sum8(unused);
-                if (unused < (uint32_t)P.n_min) {
+                if (unused < cand_min(d, P, ci)) {
                     if (sub == 0) d.status[ci] = kRejected;
                 } else {
                     for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
@@ -1259,7 +1330,7 @@ __global__ void __launch_bounds__(kBlock) k_round(DevPtrs d, Params P, int round
                 }
                 unused = group_sum8(unused);
                 lost = group_sum8(lost);
-                if (unused < (uint32_t)P.n_min) {
+                if (unused < cand_min(d, P, ci)) {
                     if (sub == 0) d.status[ci] = kRejected;
                 } else if (lost == 0) {
                     for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
@@ -1328,7 +1399,7 @@ __global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, 
                 }
             }
             unused = group_sum8(unused);
-            if (unused < (uint32_t)P.n_min && sub == 0) d.status[ci] = kRejected;
+            if (unused < cand_min(d, P, ci) && sub == 0) d.status[ci] = kRejected;
         }
         __threadfence_block();
         __syncthreads();
@@ -1361,7 +1432,7 @@ __global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, 
             }
             unused = group_sum8(unused);
             lost = group_sum8(lost);
-            if (unused < (uint32_t)P.n_min) {
+            if (unused < cand_min(d, P, ci)) {
                 if (sub == 0) d.status[ci] = kRejected;
             } else if (lost == 0) {
                 for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
@@ -2129,20 +2200,26 @@ void launch_seeds(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t 
 }
 
 void launch_count(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
-    k_count<<<kCountBlocks, kBlock, 0, s>>>(d, c, P);
+    if (P.cyl_ext >= 0)
+        k_count<true><<<kCountBlocks, kBlock, 0, s>>>(d, c, P);
+    else
+        k_count<false><<<kCountBlocks, kBlock, 0, s>>>(d, c, P);
 }
 
-void launch_candidates(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {
+void launch_candidates(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
     scan_excl<true>(d.seed_n, &d.cnt->n_seeds, (uint32_t)c.seed_cap, d.scan_part, d.cand_pos,
                     &d.cnt->n_cand, s);
-    k_cand_scatter<<<blocks_for(c.seed_cap, kPersistentBlocks), kBlock, 0, s>>>(d, c);
+    k_cand_scatter<<<blocks_for(c.seed_cap, kPersistentBlocks), kBlock, 0, s>>>(d, c, P);
 }
 
 void launch_members(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
     scan_excl(d.cand_n, &d.cnt->n_cand, c.cand_cap, d.scan_part, d.mem_off, &d.cnt->n_members, s);
-    k_members<EMT_MEMBER_LANES><<<blocks_for((unsigned long long)EMT_MEMBER_LANES * c.cand_cap,
-                                            kPersistentBlocks),
-                                 kBlock, 0, s>>>(d, c, P);
+    const uint32_t nb =
+        blocks_for((unsigned long long)EMT_MEMBER_LANES * c.cand_cap, kPersistentBlocks);
+    if (P.cyl_ext >= 0)
+        k_members<EMT_MEMBER_LANES, true><<<nb, kBlock, 0, s>>>(d, c, P);
+    else
+        k_members<EMT_MEMBER_LANES, false><<<nb, kBlock, 0, s>>>(d, c, P);
 }
 
 void launch_merge_init(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {

@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libemt.so")
 
-EMT_ABI_VERSION = 1
+EMT_ABI_VERSION = 2
 EMT_OK, EMT_EINVAL, EMT_ERANGE, EMT_ENOMEM, EMT_EDEVICE, EMT_EOVERFLOW = 0, -1, -2, -3, -4, -5
 EMT_F_STATS, EMT_F_FP64_FIT_ALWAYS, EMT_F_DEVICE_PTRS = 0x1, 0x2, 0x4
 STAGES = ("stage", "bin", "seed", "count", "members", "merge", "fit", "out")
@@ -32,7 +32,8 @@ class EmtConfig(C.Structure):
     _fields_ = [("abi_version", C.c_uint32), ("seed_dist", C.c_int32),
                 ("tol_radius", C.c_int32), ("min_grains", C.c_int32),
                 ("cell", C.c_int32 * 3), ("device", C.c_int32),
-                ("flags", C.c_uint32), ("hbm_budget", C.c_uint64), ("stream", C.c_void_p)]
+                ("flags", C.c_uint32), ("hbm_budget", C.c_uint64), ("stream", C.c_void_p),
+                ("cyl_ext", C.c_int32), ("thr_slope", C.c_int32 * 2), ("thr_max", C.c_int32)]
 
 
 class EmtViewIn(C.Structure):
@@ -160,6 +161,8 @@ def emt_default_config(**overrides) -> EmtConfig:
     for k, v in overrides.items():
         if k == "cell":
             cfg.cell = (C.c_int32 * 3)(*v)
+        elif k == "thr_slope":
+            cfg.thr_slope = (C.c_int32 * 2)(*v)
         else:
             setattr(cfg, k, v)
     return cfg

@@ -49,7 +49,8 @@ int main(void) {
   S(emt_config) S(emt_view_in) S(emt_track) S(emt_view_stats) S(emt_view_out) S(emt_call_stats)
   S(emt_served) S(emt_server_stats) S(emt_stack_geom)
   O(emt_stack_geom, threshold) O(emt_stack_geom, pitch_den)
-  O(emt_config, hbm_budget) O(emt_config, stream) O(emt_track, slope) O(emt_track, t_end)
+  O(emt_config, hbm_budget) O(emt_config, stream) O(emt_config, cyl_ext)
+  O(emt_config, thr_slope) O(emt_config, thr_max) O(emt_track, slope) O(emt_track, t_end)
   O(emt_view_out, tracks) O(emt_view_out, stats) O(emt_call_stats, ms) O(emt_call_stats, ms_total)
   O(emt_served, tracks) O(emt_served, stats) O(emt_served, t_done_ms)
   O(emt_server_stats, busy_ms) O(emt_server_stats, elapsed_ms)
@@ -69,6 +70,9 @@ int main(void) {
         "emt_view_out": C.sizeof(emt.EmtViewOut), "emt_call_stats": C.sizeof(emt.EmtCallStats),
         "emt_config.hbm_budget": emt.EmtConfig.hbm_budget.offset,
         "emt_config.stream": emt.EmtConfig.stream.offset,
+        "emt_config.cyl_ext": emt.EmtConfig.cyl_ext.offset,
+        "emt_config.thr_slope": emt.EmtConfig.thr_slope.offset,
+        "emt_config.thr_max": emt.EmtConfig.thr_max.offset,
         "emt_track.slope": emt.EmtTrack.slope.offset,
         "emt_track.t_end": emt.EmtTrack.t_end.offset,
         "emt_view_out.tracks": emt.EmtViewOut.tracks.offset,
@@ -94,6 +98,7 @@ def test_defaults_and_strerror(emt):
     cfg = emt.emt_default_config()
     assert cfg.abi_version == emt.EMT_ABI_VERSION
     assert (cfg.seed_dist, cfg.tol_radius, cfg.min_grains) == (2500, 50, 8)
+    assert (cfg.cyl_ext, tuple(cfg.thr_slope), cfg.thr_max) == (-1, (0, 1), 0)
     for rc in (0, -1, -2, -3, -4, -5):
         assert emt.emt_strerror(rc)
     assert emt.emt_strerror(12345) == "unknown error"
@@ -103,11 +108,21 @@ def test_defaults_and_strerror(emt):
     ("abi_version", 7, -1), ("flags", 0x100, -1), ("cell", (-5, 0, 0), -1), ("device", -1, -1),
     ("seed_dist", 0, -2), ("seed_dist", 4097, -2), ("tol_radius", -1, -2),
     ("tol_radius", 2500, -2), ("min_grains", 1, -2), ("min_grains", 1 << 20, -2),
-    ("cell", (0, 0, (1 << 18) + 1), -2),
+    ("cell", (0, 0, (1 << 18) + 1), -2), ("cyl_ext", -2, -2), ("cyl_ext", (1 << 18) + 1, -2),
+    ("thr_slope", (-1, 1), -2), ("thr_slope", (1025, 1), -2), ("thr_slope", (1, 0), -2),
+    ("thr_slope", (1, 1025), -2), ("thr_max", -1, -2), ("thr_max", 7, -2),
+    ("thr_max", 1 << 20, -2),
 ])
 def test_validate_rejects_bad_config(emt, field, value, rc):
     cfg = emt.emt_default_config(**{field: value})
     assert emt.emt_validate(cfg) == rc
+
+
+@pytest.mark.parametrize("field,value", [
+    ("cyl_ext", 0), ("cyl_ext", 1 << 18), ("thr_slope", (1024, 1024)), ("thr_slope", (0, 1)),
+    ("thr_max", 8), ("thr_max", (1 << 20) - 1)])
+def test_validate_accepts_variant_limits(emt, field, value):
+    assert emt.emt_validate(emt.emt_default_config(**{field: value})) == 0
 
 
 def test_validate_views(emt):

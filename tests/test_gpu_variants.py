@@ -1,0 +1,77 @@
+"""The acceptance variants on the GPU against the oracle: the paper's own
+threshold n > 5 (n_min = 6), finite cylinders and the angle-dependent
+grain-count threshold (Sec. 4, Fig. 9c), alone and together, on single
+views and in a batched call."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1311_5334_amd import synth
+from parity import assert_view_parity
+
+pytestmark = pytest.mark.gpu
+
+SETTINGS = {
+    "paper_n_gt_5": dict(min_grains=6),
+    "segment_only": dict(cyl_ext=0),
+    "cyl_5um": dict(cyl_ext=500),
+    "cyl_20um": dict(cyl_ext=2000),
+    "slope_1": dict(thr_slope=(1, 1)),
+    "slope_2.5_cap": dict(thr_slope=(5, 2), thr_max=12),
+    "all": dict(min_grains=6, cyl_ext=700, thr_slope=(3, 4), thr_max=14),
+}
+
+
+def _oracle_kw(cfg):
+    return dict(n_min=cfg.get("min_grains", 8), cyl_ext=cfg.get("cyl_ext", -1),
+                thr_slope=cfg.get("thr_slope", (0, 1)), thr_max=cfg.get("thr_max", 0))
+
+
+@pytest.fixture(scope="module")
+def emt():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1311_5334_amd import emt as m
+    m.load()
+    return m
+
+
+@pytest.mark.parametrize("name", list(SETTINGS))
+def test_variant_matches_oracle(emt, name):
+    from oracle import oracle
+    cfg = SETTINGS[name]
+    views = [synth.make_c1(i) for i in range(3)] + [synth.make_c2(1)]
+    with emt.Tracker(device=0, **cfg) as tr:
+        for v in views:
+            print(f"{name}: {v.config} view, {v.n} grains", flush=True)
+            got = tr([v.xyz])[0]
+            ref = oracle.track_view(v.xyz, **_oracle_kw(cfg))
+            assert_view_parity(v.xyz, got, ref)
+        sys.stdout.flush()
+
+
+def test_variants_change_results(emt):
+    """Each variant does something on a full view: fewer candidates than the
+    default, and for n_min = 6 more."""
+    v = synth.make_c2(1)
+    with emt.Tracker(device=0) as tr:
+        base = tr([v.xyz])[0]["n_candidates"]
+    for name, cfg in SETTINGS.items():
+        with emt.Tracker(device=0, **cfg) as tr:
+            n = tr([v.xyz])[0]["n_candidates"]
+        if name == "paper_n_gt_5":
+            assert n > base
+        elif name != "all":
+            assert n < base, name
+
+
+def test_batched_variant_matches_oracle(emt):
+    from oracle import oracle
+    cfg = SETTINGS["all"]
+    views = [synth.make_c3(i) for i in range(12)]
+    views = [v for v in views if v.n < 12000][:6]
+    with emt.Tracker(device=0, **cfg) as tr:
+        got = tr([v.xyz for v in views])
+    for v, g in zip(views, got):
+        assert_view_parity(v.xyz, g, oracle.track_view(v.xyz, **_oracle_kw(cfg)))
