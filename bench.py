@@ -323,6 +323,32 @@ def measure_module(emt, seed: int = 0, calls: int = 3) -> dict:
                              for r in eff.table()]}
 
 
+def measure_variants(emt, torch, view, calls: int = 20) -> dict:
+    """The plain path on the benchmark view under the acceptance variants:
+    device time per view and the candidates and tracks each leaves."""
+    dev = torch.from_numpy(view.xyz).to("cuda:0").contiguous()
+    torch.cuda.synchronize()
+    out = {}
+    for name, cfg in (("default", {}), ("paper_n_gt_5", {"min_grains": 6}),
+                      ("cylinder_5um", {"cyl_ext": 500}), ("segment_only", {"cyl_ext": 0}),
+                      ("angle_threshold_b1", {"thr_slope": (1, 1)})):
+        with emt.Tracker(device=0, flags=emt.EMT_F_DEVICE_PTRS | emt.EMT_F_STATS, **cfg) as tr:
+            for _ in range(3):
+                r = tr([dev])[0]
+            ms, cnt = [], []
+            for _ in range(calls):
+                r = tr([dev])[0]
+                st = tr.stats()
+                ms.append(sum(st["ms"].values()))
+                cnt.append(st["ms"]["count"])
+        out[name] = {"config": {k: list(v) if isinstance(v, tuple) else v for k, v in cfg.items()},
+                     "device_ms_per_view": round(float(np.median(ms)), 4),
+                     "count_ms": round(float(np.median(cnt)), 4),
+                     "grains_per_s": round(view.n / (float(np.median(ms)) * 1e-3), 1),
+                     "candidates": int(r["n_candidates"]), "tracks": int(len(r["tracks"]))}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,10 +356,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--view-index", type=int, default=0)
-    ap.add_argument("--forms", default="c3,c5,c4,stacks,raw,module",
+    ap.add_argument("--forms", default="c3,c5,c4,stacks,raw,module,variants",
                     help="other forms to add to the line (comma list of c3, c5 batched, "
-                         "c4 served, stacks for grain recognition, raw for filtering and "
-                         "module for the efficiency method; '' for none)")
+                         "c4 served, stacks for grain recognition, raw for filtering, "
+                         "module for the efficiency method and variants for the acceptance "
+                         "variants; '' for none)")
     ap.add_argument("--served-requests", type=int, default=5000)
     ap.add_argument("--served-warmup", type=int, default=500)
     ap.add_argument("--form-calls", type=int, default=5)
@@ -452,6 +479,11 @@ def main() -> int:
                 "300 x 250 um each, cosmic rays 150/mm^2 at 42 grains/100 um, cos^3 zenith "
                 "angles to tan 2.5, fog 3/1000 um^3, 2 electrons a view; layers 0, 1, 3 "
                 "predict layer 2; fakes with layer 2 displaced by 1 mm")
+        elif f == "variants":
+            forms["acceptance_variants"] = measure_variants(emt, torch, view)
+            forms["acceptance_variants"]["workload"] = (
+                "the c2 benchmark view under each acceptance variant; device time of the "
+                "whole path per view")
         elif f == "c4":
             vs = [synth.make_c4(i) for i in range(96)]
             forms["served_c4"] = measure_served(emt, vs, args.served_requests, args.served_warmup)

@@ -367,8 +367,11 @@ struct Pencil {
     // part/nparts: this lane walks the part-th of nparts equal slices of the
     // e cells, so that several lanes can share one long line. No divisions:
     // reciprocals (within 1 ulp) are covered by the kMargin widening.
+    // ext >= 0: a finite cylinder, whose grains project at most ext units
+    // beyond the seed grains; the walk then covers only that stretch.
     __device__ __forceinline__ void init(const ViewGrid *__restrict__ Gp, int4 g, int idx, int idy,
-                                         int idz, int r, bool valid, int part, int nparts) {
+                                         int idz, int r, bool valid, int part, int nparts,
+                                         int ext = -1) {
         nx = Gp->dims[0];
         const int ny = Gp->dims[1];
         const int nz = Gp->dims[2];
@@ -376,6 +379,7 @@ struct Pencil {
         off = Gp->cell_off;
         const float rr = (float)r + kMargin;
         // the line is undirected: take the direction with d_x >= 0
+        const bool flipped = idx < 0;
         if (idx < 0) {
             idx = -idx;
             idy = -idy;
@@ -409,6 +413,16 @@ struct Pencil {
             t2 = ((float)(nz * czi - 1) + rr - gz) * iz;
             tlo = fmaxf(tlo, fminf(t1, t2));
             thi = fminf(thi, fmaxf(t1, t2));
+        }
+        if (ext >= 0) {
+            // the seed grains sit at t = 0 and t = 1 (t = -1 once flipped);
+            // grains of the cylinder project within (ext + rr) / |d| beyond
+            // them (widened for the approximate reciprocal square root)
+            const float reach = ((float)ext + rr) * 1.001f *
+                                __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+            const float s0 = flipped ? -1.0f : 0.0f;
+            tlo = fmaxf(tlo, s0 - reach);
+            thi = fminf(thi, s0 + 1.0f + reach);
         }
         const bool e_is_y = abs(idy) >= abs(idz);
         const float ge = e_is_y ? gy : gz;
@@ -847,7 +861,8 @@ __global__ void __launch_bounds__(kBlock) k_members(DevPtrs d, Caps c, Params P)
         }
         wave_lds_sync();
         Pencil W;
-        W.init(&d.grids[v], gi, dx, dy, dz, P.r, valid && ncap > 0, sub, kPer);
+        W.init(&d.grids[v], gi, dx, dy, dz, P.r, valid && ncap > 0, sub, kPer,
+               kFinite ? P.cyl_ext : -1);
         Run s0 = {0, 0}, s1 = {0, 0}, s2 = {0, 0}, s3 = {0, 0};
         uint32_t qn = 0, nr = 0;
         for (;;) {
@@ -1080,7 +1095,7 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
                 Q.pa[cur] = make_int4(dx, dy, dz, __float_as_int(L.tlo));
                 Q.pb[cur] = make_int4((int)L.ex, (int)L.ey, (int)L.ez, __float_as_int(L.thi));
                 Q.cnt[cur] = 0;
-                W.init(&d.grids[v], gi, dx, dy, dz, P.r, true, 0, 1);
+                W.init(&d.grids[v], gi, dx, dy, dz, P.r, true, 0, 1, kFinite ? P.cyl_ext : -1);
                 have = true;
             }
             next = min(end, next + (uint32_t)__popcll(wm));
