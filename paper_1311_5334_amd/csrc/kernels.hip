@@ -230,11 +230,25 @@ __global__ void __launch_bounds__(kBlock) k_bbox(const int32_t *xyz, ViewGrid *g
             hi[m] = max(hi[m], __shfl_xor(hi[m], o));
         }
     }
-    if (lane_id() == 0 && n > 0) {
+    // one atomic per workgroup and value: atomics on the six words of a
+    // view serialise in L2, so they are reduced across the waves first
+    __shared__ int s_box[kBlock / 64][6];
+    const int wave = threadIdx.x >> 6;
+    if (lane_id() == 0)
         for (int m = 0; m < 3; ++m) {
-            atomicMin(&grids[v].lo[m], lo[m]);
-            atomicMax(&grids[v].hi[m], hi[m]);
+            s_box[wave][m] = lo[m];
+            s_box[wave][3 + m] = hi[m];
         }
+    __syncthreads();
+    if (threadIdx.x < 6 && n > 0) {
+        const int m = (int)threadIdx.x;
+        int b = s_box[0][m];
+        for (int w = 1; w < kBlock / 64; ++w)
+            b = m < 3 ? min(b, s_box[w][m]) : max(b, s_box[w][m]);
+        if (m < 3)
+            atomicMin(&grids[v].lo[m], b);
+        else
+            atomicMax(&grids[v].hi[m - 3], b);
     }
 }
 
