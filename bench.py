@@ -38,6 +38,7 @@ COUNT_KERNEL_SRCS = [os.path.join(ROOT, "paper_1311_5334_amd", "csrc", f)
                      for f in ("kernels.hip", "cell_table.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "count_traffic.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "count_valu.json")
+BIN_BYTES_PER_GRAIN = 44
 GRAIN_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grain_traffic.json")
 
 
@@ -140,7 +141,33 @@ def measure_batch(emt, torch, views, calls: int, warmup: int) -> dict:
                      "candidates": st0["n_candidates"], "tracks": st0["n_tracks"],
                      "merge_rounds": st0["merge_rounds"]},
             "count_roofline": {"achieved": round(achieved, 3), "unit": "Tops/s",
-                               "frac": round(achieved / (VALU_PEAK_OPS / 1e12), 4)}}
+                               "frac": round(achieved / (VALU_PEAK_OPS / 1e12), 4)},
+            # binning: two reads of the 12-byte grains, one 16-byte sorted
+            # write and the cell counters, about 44 bytes a grain
+            "bin_roofline": {"achieved": round(BIN_BYTES_PER_GRAIN * grains /
+                                               (st["ms"]["bin"] * 1e-3) / 1e9, 1),
+                             "unit": "GB/s", "bytes_per_grain": BIN_BYTES_PER_GRAIN,
+                             "frac": round(BIN_BYTES_PER_GRAIN * grains / (st["ms"]["bin"] * 1e-3)
+                                           / 1e9 / HBM_PEAK_GBS, 4)}}
+
+
+def measured_copy_gbs(torch, nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """A plain device-to-device copy of nbytes, timed with events: bytes
+    read plus bytes written per second, the streaming rate HBM gives a
+    simple kernel on this GPU."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return 2.0 * nbytes / sec / 1e9
 
 
 def measure_served(emt, views, n_req: int, warmup: int, batch: int = 16,
@@ -499,6 +526,14 @@ def main() -> int:
             forms["served_c4"]["workload"] = (
                 "c4: Poisson stream drawn from 96 views of 100^2, 200^2 or 350^2 x 50 um, "
                 "fog 1-10/1000 um^3, 2449 tracks/mm^2; two pipelines, up to 16 views a batch")
+    # the streaming rate a plain copy gets, beside the 8 TB/s specification
+    copy_gbs = measured_copy_gbs(torch)
+    out["hbm_copy_measured_GBs"] = round(copy_gbs, 1)
+    for key in ("grain_recognition", "filtering"):
+        if key in forms:
+            rf = forms[key]["roofline"]
+            rf["measured_peak"] = round(copy_gbs, 1)
+            rf["frac_of_measured"] = round(rf["achieved"] / copy_gbs, 4)
     if forms:
         out["forms"] = forms
     if not args.no_cpu_baseline:
