@@ -8,7 +8,9 @@ in calls of 16 views and, separately, as one stream through the server;
 the two must agree byte for byte), c5 32 (one call). Every view is compared
 with the oracle by tests/parity.py. Also 16 filtered stacks of the paper's
 1280x1024x40 view (fog 0.5-4 per 1000 um^3, thresholds 40-120) go through
-the grain recognition, whose grain lists must equal the oracle's exactly.
+the grain recognition, whose grain lists must equal the oracle's exactly,
+and the c1 views and 8 c2 views are tracked again under three acceptance
+variants (n_min 6; a 5 um finite cylinder; an angle-dependent threshold).
 The oracle runs in a pool of worker processes forked before the GPU is
 touched; the summary also gives the oracle's whole-pool tracking rate
 (grains per second of wall time on those cores).
@@ -32,6 +34,19 @@ from paper_1311_5334_amd import synth  # noqa: E402
 
 COUNTS = {"c5": 32, "c4": 300, "c3": 512, "c2": 32, "c1": 100}
 N_STACKS = 16
+VARIANTS = {"n_min_6": dict(min_grains=6), "cyl_5um": dict(cyl_ext=500),
+            "slope_1_cap_20": dict(thr_slope=(1, 1), thr_max=20)}
+N_VARIANT_C2 = 8
+
+
+def _variant_job(job):
+    from oracle import oracle
+    name, cfg, idx = job
+    v = synth.make_view(cfg, idx)
+    c = VARIANTS[name]
+    ref = oracle.track_view(v.xyz, n_min=c.get("min_grains", 8), cyl_ext=c.get("cyl_ext", -1),
+                            thr_slope=c.get("thr_slope", (0, 1)), thr_max=c.get("thr_max", 0))
+    return name, cfg, idx, ref
 
 
 def _stack(i):
@@ -104,6 +119,10 @@ def main() -> int:
     it = pool.imap_unordered(_oracle_job, jobs, chunksize=1)
     n_st = max(1, int(N_STACKS * args.scale))
     it_st = pool.imap_unordered(_stack_job, range(n_st), chunksize=1)
+    vjobs = [(name, cfg, i) for name in VARIANTS
+             for cfg, n in (("c1", COUNTS["c1"]), ("c2", N_VARIANT_C2))
+             for i in range(max(1, int(n * args.scale)))]
+    it_var = pool.imap_unordered(_variant_job, vjobs, chunksize=1)
     got, served = _gpu_all(jobs)
     from paper_1311_5334_amd import emt
     st_fail, st_grains = 0, 0
@@ -113,6 +132,15 @@ def main() -> int:
             st = _stack(i)
             st_got[i] = tr.find_grains(st.img, st.threshold)
     print(f"gpu: {n_st} stacks recognised", flush=True)
+    var_got = {}
+    for name, c in VARIANTS.items():
+        with emt.Tracker(device=0, **c) as tr:
+            for cfg in ("c1", "c2"):
+                idxs = [i for (nm, cf, i) in vjobs if nm == name and cf == cfg]
+                res = tr([synth.make_view(cfg, i).xyz for i in idxs])
+                for i, r in zip(idxs, res):
+                    var_got[(name, cfg, i)] = r
+    print(f"gpu: {len(var_got)} variant views tracked", flush=True)
     stats = {cfg: {"views": 0, "grains": 0, "cpu_s": 0.0, "fail": 0, "first": "", "tracks": 0}
              for cfg in COUNTS}
     serve_mismatch = 0
@@ -147,6 +175,15 @@ def main() -> int:
         if not np.array_equal(st_got[i], ref):
             st_fail += 1
     print(f"oracle: {n_st} stacks compared", flush=True)
+    var_fail, var_first = 0, ""
+    from parity import assert_view_parity as _avp
+    for name, cfg, idx, ref in it_var:
+        try:
+            _avp(synth.make_view(cfg, idx).xyz, var_got[(name, cfg, idx)], ref)
+        except AssertionError as e:
+            var_fail += 1
+            var_first = var_first or f"{name} {cfg}[{idx}]: {e!r}"[:200]
+    print(f"oracle: {len(vjobs)} variant views compared", flush=True)
     pool.close()
     pool.join()
     fails = sum(st["fail"] for st in stats.values())
@@ -171,6 +208,10 @@ def main() -> int:
               f"{stats['c4']['views']}.", "",
               f"Grain recognition: {n_st} stacks of 1280x1024x40 pixels, {st_grains:,} grains; "
               f"{st_fail} stacks differ from the oracle's grain list.", "",
+              f"Acceptance variants ({', '.join(VARIANTS)}): {len(vjobs)} views (all c1 views "
+              f"and {N_VARIANT_C2} c2 views under each, one call per variant and config); "
+              f"{var_fail} differ from the oracle." + (f" First: {var_first}" if var_first else ""),
+              "",
               f"Oracle: {tot_g:,} grains in {tot_cpu:.0f} s of single-thread CPU time "
               f"({tot_g / tot_cpu:,.0f} grains/s per core); {args.procs} worker processes "
               f"finished in {wall:.0f} s of wall time ({tot_g / wall:,.0f} grains/s for the "
@@ -182,7 +223,7 @@ def main() -> int:
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     open(args.out, "w").write(text)
     print(text, flush=True)
-    return 1 if fails or serve_mismatch or st_fail else 0
+    return 1 if fails or serve_mismatch or st_fail or var_fail else 0
 
 
 if __name__ == "__main__":

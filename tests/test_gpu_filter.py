@@ -100,3 +100,35 @@ def test_bad_geometry_is_rejected(emt, tracker):
         rc = emt.load().emt_filter_stack(tracker.ctx, raw.ctypes.data, C.byref(g),
                                          gain.ctypes.data, thr.ctypes.data, out.ctypes.data)
         assert rc == emt.EMT_ERANGE, shape
+
+
+def test_largest_stack_in_place(emt):
+    """2^31 pixels, the largest stack accepted, filtered in place on the
+    device; checked at 200k sampled pixels and the first and last pixel of
+    every frame against the oracle's per-pixel definition."""
+    import torch
+    from oracle.filtering import filter_stack
+    nz, ny, nx = 128, 1024, 16384
+    _say("largest filter stack: 2 GiB")
+    raw = torch.empty((nz, ny, nx), dtype=torch.uint8, device="cuda:0")
+    base = torch.arange(ny * nx, device="cuda:0", dtype=torch.int64)
+    for z in range(nz):  # a hashed pattern, one frame at a time
+        raw[z] = (((base + z * ny * nx) * 2654435761 >> 13) & 255).to(torch.uint8).view(ny, nx)
+    g = torch.Generator(device="cuda:0").manual_seed(5)
+    gain = torch.randint(0, 1024, (ny, nx), device="cuda:0", generator=g, dtype=torch.int32)
+    gain = gain.to(torch.int16)
+    thr = torch.randint(0, 64, (ny, nx), device="cuda:0", generator=g, dtype=torch.int32)
+    thr = thr.to(torch.uint8)
+    rng = np.random.default_rng(3)
+    idx = np.concatenate([rng.integers(0, nz * ny * nx, 200000),
+                          np.arange(nz) * ny * nx, np.arange(1, nz + 1) * ny * nx - 1])
+    it = torch.from_numpy(idx).to("cuda:0")
+    before = raw.view(-1)[it].cpu().numpy()
+    with emt.Tracker(device=0, flags=emt.EMT_F_DEVICE_PTRS) as t:
+        t.filter_stack(raw, gain, thr, out=raw)
+    after = raw.view(-1)[it].cpu().numpy()
+    plane = idx % (ny * nx)
+    gm = gain.view(-1).cpu().numpy().view(np.uint16)[plane]
+    tm = thr.view(-1).cpu().numpy()[plane]
+    expect = filter_stack(before.reshape(1, 1, -1), gm.reshape(1, -1), tm.reshape(1, -1))
+    assert np.array_equal(after, expect.reshape(-1))
