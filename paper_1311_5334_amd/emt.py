@@ -263,6 +263,9 @@ def emt_find_grains(ctx, stack, threshold: int, device_ptrs: bool = False, max_o
         cap = max_out if max_out is not None else max(1024, stack.numel() // 64)
         if out is None:
             out = torch.empty((cap, 3), dtype=torch.int32, device=stack.device)
+        if not (out.is_cuda and out.dtype == torch.int32 and out.is_contiguous()
+                and out.dim() == 2 and out.shape[1] == 3):
+            raise TypeError("out must be a contiguous (n, 3) int32 CUDA tensor")
         cap = min(cap, out.shape[0])
         rc = lib.emt_find_grains(ctx, stack.data_ptr(), C.byref(g), out.data_ptr(), cap,
                                  C.byref(n))
@@ -304,6 +307,9 @@ def emt_filter_stack(ctx, raw, gain, thr, device_ptrs: bool = False, out=None):
                                 "(8-bit stack and thresholds, 16-bit gains)")
         if out is None:
             out = torch.empty_like(raw)
+        if not (out.is_cuda and out.is_contiguous() and out.element_size() == 1
+                and out.numel() == raw.numel()):
+            raise TypeError("out must be a contiguous 8-bit CUDA tensor of the stack's size")
         rc = lib.emt_filter_stack(ctx, raw.data_ptr(), C.byref(g), gain.data_ptr(),
                                   thr.data_ptr(), out.data_ptr())
         if rc != EMT_OK:
@@ -313,6 +319,9 @@ def emt_filter_stack(ctx, raw, gain, thr, device_ptrs: bool = False, out=None):
     gm = np.ascontiguousarray(np.asarray(gain, dtype=np.uint16))
     tm = np.ascontiguousarray(np.asarray(thr, dtype=np.uint8))
     res = np.empty_like(a) if out is None else out
+    if not (isinstance(res, np.ndarray) and res.dtype == np.uint8 and res.size == a.size
+            and res.flags.c_contiguous and res.flags.writeable):
+        raise TypeError("out must be a writable contiguous uint8 array of the stack's size")
     rc = lib.emt_filter_stack(ctx, a.ctypes.data, C.byref(g), gm.ctypes.data, tm.ctypes.data,
                               res.ctypes.data)
     if rc != EMT_OK:

@@ -197,3 +197,16 @@ def test_filter_stack_rejects_null_without_device(emt):
     g = emt.stack_geom((4, 8, 16), 0)
     assert lib.emt_filter_stack(None, None, C.byref(g), None, None, None) == -1
     assert lib.emt_filter_stack(None, None, None, None, None, None) == -1
+
+
+def test_filter_binding_rejects_a_wrong_output_buffer(emt):
+    """The binding refuses an output array the library would write past."""
+    raw = np.zeros((2, 3, 8), np.uint8)
+    gain = np.zeros((3, 8), np.uint16)
+    thr = np.zeros((3, 8), np.uint8)
+    for bad in (np.zeros(10, np.uint8), np.zeros((2, 3, 8), np.int32),
+                np.zeros((2, 3, 16), np.uint8)[:, :, ::2]):
+        with pytest.raises(TypeError):
+            emt.emt_filter_stack(None, raw, gain, thr, out=bad)
+    with pytest.raises(ValueError):
+        emt.emt_filter_stack(None, raw, np.zeros((3, 4), np.uint16), thr)

@@ -164,6 +164,26 @@ def test_device_pointers_and_overflow(emt):
     assert tr["tracks"].tobytes() == ref_tr["tracks"].tobytes()
 
 
+def test_overflow_reports_the_total(emt, tracker):
+    """Through the C ABI: with room for fewer grains than found, EOVERFLOW,
+    n_out the true total, and the first max_out grains written in order."""
+    import ctypes as C
+    from oracle.grains import find_grains
+    st = synth_stack.make_small_stack(8, (96, 64, 12), n_grains=30)
+    ref, _ = find_grains(st.img, st.threshold)
+    assert len(ref) > 10
+    g = emt.stack_geom(st.img.shape, st.threshold)
+    out = np.full((7, 3), -1, np.int32)
+    n = C.c_uint32(0)
+    rc = emt.load().emt_find_grains(tracker.ctx, st.img.ctypes.data, C.byref(g),
+                                    out.ctypes.data, 7, C.byref(n))
+    assert rc == emt.EMT_EOVERFLOW and n.value == len(ref)
+    assert np.array_equal(out, ref[:7])
+    rc = emt.load().emt_find_grains(tracker.ctx, st.img.ctypes.data, C.byref(g), None, 0,
+                                    C.byref(n))
+    assert rc == emt.EMT_EOVERFLOW and n.value == len(ref)
+
+
 def test_bad_geometry_is_rejected(emt, tracker):
     import ctypes as C
     lib = emt.load()

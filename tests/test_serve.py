@@ -125,3 +125,25 @@ def test_served_submit_checks_span(emt):
         srv.submit(synth.make_c1(1).xyz, view_id=5)
         got = _collect(srv, 1)
     assert got[5]["status"] == 0
+
+
+def test_served_variant_matches_batched(emt):
+    """A server built with acceptance variants (n_min 6, a 5 um finite
+    cylinder, an angle-dependent threshold) gives every view the bytes the
+    batched call with the same configuration gives it."""
+    from paper_1311_5334_amd import synth
+    cfg = dict(min_grains=6, cyl_ext=500, thr_slope=(1, 2), thr_max=16)
+    views = [synth.make_c4(i) for i in range(8)]
+    with emt.Tracker(device=0, **cfg) as tr:
+        ref = tr([v.xyz for v in views])
+    got = {}
+    with emt.Server(n_pipes=2, max_batch_views=4, device=0, **cfg) as srv:
+        for i, v in enumerate(views):
+            srv.submit(v.xyz, view_id=i)
+        while len(got) < len(views):
+            for r in srv.poll(wait_ms=200):
+                got[r["view_id"]] = r
+    for i, r in enumerate(ref):
+        assert got[i]["status"] == 0
+        assert got[i]["tracks"].tobytes() == r["tracks"].tobytes()
+        assert np.array_equal(got[i]["grains"], r["grains"])
