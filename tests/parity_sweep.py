@@ -107,7 +107,7 @@ def _gpu_all(jobs):
 
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "parity_sweep.md"))
+    ap.add_argument("--out", default=None, help="also write the summary to this file")
     ap.add_argument("--procs", type=int, default=16)
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of each view count")
     args = ap.parse_args()
@@ -189,7 +189,8 @@ def main() -> int:
     fails = sum(st["fail"] for st in stats.values())
     lines = ["# Parity sweep: GPU library vs CPU oracle", "",
              f"Command (repo root, one MI355X): `python tests/parity_sweep.py --procs {args.procs}"
-             + (f" --scale {args.scale}" if args.scale != 1.0 else "") + "`", "",
+             + (f" --scale {args.scale}" if args.scale != 1.0 else "")
+             + (" --out <this file>" if args.out else "") + "`", "",
              "Every view below was tracked on the GPU (calls of 100 c1, 32 c2, 64 c3, 16 c4 and "
              "32 c5 views) and compared with the oracle: seed counts, candidate counts, track "
              "seeds, order, grain lists and grain order, fit axis and FP64 flag exactly; "
@@ -220,8 +221,9 @@ def main() -> int:
         if stats[cfg]["first"]:
             lines.append(f"First mismatch: {stats[cfg]['first']}")
     text = "\n".join(lines) + "\n"
-    os.makedirs(os.path.dirname(args.out), exist_ok=True)
-    open(args.out, "w").write(text)
+    if args.out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+        open(args.out, "w").write(text)
     print(text, flush=True)
     return 1 if fails or serve_mismatch or st_fail or var_fail else 0
 
