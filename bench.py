@@ -442,6 +442,32 @@ def main() -> int:
     wall = time.perf_counter() - t_start
     tr.close()
 
+    # the same loop without per-stage events (one graph launch per call
+    # instead of one per stage): the library's rate when no timing is asked
+    # for; the reported value keeps the events, which time the kernels
+    with emt.Tracker(device=0, flags=emt.EMT_F_DEVICE_PTRS) as tq:
+        for _ in range(3):
+            tq([dev])
+        torch.cuda.synchronize()
+        t_q = time.perf_counter()
+        for _ in range(args.steps):
+            tq([dev])
+        torch.cuda.synchronize()
+        wall_q = time.perf_counter() - t_q
+
+    # the same view handed over as a host array (not the reported value):
+    # each call then includes the PCIe copies of the grains in and the
+    # tracks out
+    with emt.Tracker(device=0) as th:
+        for _ in range(3):
+            th([view.xyz])
+        h_lat = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            th([view.xyz])
+            h_lat.append(time.perf_counter() - t0)
+    h_lat_ms = np.array(h_lat) * 1e3
+
     grains = view.n * args.steps
     value = grains / wall
     mm2_h = view.area_mm2 * args.steps / wall * 3600.0
@@ -534,6 +560,13 @@ def main() -> int:
             rf = forms[key]["roofline"]
             rf["measured_peak"] = round(copy_gbs, 1)
             rf["frac_of_measured"] = round(rf["achieved"] / copy_gbs, 4)
+    out["without_stage_events"] = {"grains_per_s": round(view.n * args.steps / wall_q, 1),
+                                   "ms_per_step": round(wall_q / args.steps * 1e3, 4)}
+    out["host_input"] = {"grains_per_s": round(view.n / (float(h_lat_ms.mean()) * 1e-3), 1),
+                         "latency_ms": {"p50": round(float(np.percentile(h_lat_ms, 50)), 4),
+                                        "p99": round(float(np.percentile(h_lat_ms, 99)), 4)},
+                         "note": "the c2 view as a host array: PCIe copies of grains and "
+                                 "results inside each call"}
     if forms:
         out["forms"] = forms
     if not args.no_cpu_baseline:
