@@ -475,6 +475,8 @@ def main() -> int:
     ms = {k: float(np.mean([s[k] for s in stage_ms])) for k in stage_ms[0]}
     count_s = ms["count"] * 1e-3
     tests = stats["n_tests"]
+    if count_s <= 0:
+        raise RuntimeError("the library reported no device time for the counting stage")
     achieved = tests * OPS_PER_TEST / count_s / 1e12
     peak = VALU_PEAK_OPS / 1e12
     out = {

@@ -366,3 +366,16 @@ def test_merge_rounds_adapt_without_changing_results(emt):
     for a, b, c in zip(ref, got, again):
         assert a["tracks"].tobytes() == b["tracks"].tobytes() == c["tracks"].tobytes()
         assert np.array_equal(a["grains"], b["grains"]) and np.array_equal(a["grains"], c["grains"])
+
+
+def test_stats_time_every_stage(emt):
+    """With EMT_F_STATS every stage of a full view reports a positive device
+    time (the counting kernel's roofline in the benchmark rests on it)."""
+    from paper_1311_5334_amd import synth
+    v = synth.make_c2(0)
+    with emt.Tracker(device=0, flags=emt.EMT_F_STATS) as tr:
+        tr([v.xyz])
+        tr([v.xyz])
+        st = tr.stats()
+    assert all(ms > 0 for ms in st["ms"].values()), st["ms"]
+    assert st["n_tests"] > 0 and st["n_seeds"] > 0
