@@ -113,7 +113,8 @@ def make_module(seed: int = 0, nx_views: int = 8, ny_views: int = 8,
                 pts.append(fog)
                 pts.extend(el)
                 mod.views.append(ModuleView(layer, ix, iy, o, None))
-        allp = np.concatenate([q for q in pts if len(q)], axis=0)
+        nonempty = [q for q in pts if len(q)]
+        allp = np.concatenate(nonempty, axis=0) if nonempty else np.zeros((0, 3))
         allp = allp[(allp[:, 2] >= z0) & (allp[:, 2] < z1)]
         vx = np.floor(allp[:, 0] / VIEW_XY[0]).astype(np.int64)
         vy = np.floor(allp[:, 1] / VIEW_XY[1]).astype(np.int64)

@@ -127,3 +127,12 @@ def test_oracle_tracks_are_efficient_on_a_small_module():
     eff = module.measure_efficiency(m, module.layer_tracks(m, res), margin=10.0)
     assert eff.selected.sum() > 20
     assert eff.efficiency >= 0.95
+
+
+def test_empty_module_has_empty_views_and_no_references():
+    m = module.make_module(9, nx_views=2, ny_views=2, cosmics_per_mm2=0.0,
+                           fog_per_1000_um3=0.0, electrons_per_view=0)
+    assert all(len(v.xyz) == 0 and v.xyz.shape == (0, 3) for v in m.views)
+    res = [{"tracks": np.zeros(0, synth_track_dtype())} for _ in m.views]
+    eff = module.measure_efficiency(m, module.layer_tracks(m, res))
+    assert eff.selected.sum() == 0 and eff.efficiency == 0.0 and eff.fake_rate == 0.0
