@@ -160,3 +160,34 @@ def test_recovers_isolated_rendered_spots():
         assert abs(got[k, 0] - c[0]) < 0.25 * synth_stack.pitch_um(0) + 0.01
         assert abs(got[k, 1] - c[1]) < 0.25 * synth_stack.pitch_um(1) + 0.01
         assert abs(got[k, 2] - c[2]) < 0.5 * synth_stack.pitch_um(2)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_local_maxima_match_a_library_maximum_filter(seed):
+    """The rule as a textbook local maximum of a key that orders pixels by
+    pulse height, then earlier first: key = v N + (N - 1 - flat index). A
+    grain is a pixel above threshold whose key is the maximum of its
+    3 x 3 x 3 block (missing neighbours below every key). scipy's
+    maximum_filter and center_of_mass state both steps independently."""
+    from scipy import ndimage
+    rng = np.random.default_rng(40 + seed)
+    nz, ny, nx = 6, 9, 12
+    img = rng.integers(0, 256, (nz, ny, nx)).astype(np.uint8)
+    if seed % 2:
+        img = (img // 32 * 32).astype(np.uint8)   # eight levels: ties everywhere
+    n = img.size
+    key = img.astype(np.int64) * n + (n - 1 - np.arange(n).reshape(img.shape))
+    mx = ndimage.maximum_filter(key, size=3, mode="constant", cval=-1)
+    thr = 100
+    expect = np.argwhere((img > thr) & (key == mx))
+    xyz, pix = find_grains(img, thr)
+    assert len(expect) > 0
+    assert pix.tolist() == expect.tolist()
+    for (z, y, x), c in zip(pix, xyz):
+        z0, y0, x0 = max(z - 1, 0), max(y - 1, 0), max(x - 1, 0)
+        block = img[z0:z + 2, y0:y + 2, x0:x + 2].astype(np.float64)
+        cz, cy, cx = ndimage.center_of_mass(block)
+        pos = (x0 + cx, y0 + cy, z0 + cz)
+        for m in range(3):
+            # nearest 0.01 um of the exact position: within half a unit
+            assert abs(c[m] - pos[m] * P_NUM[m] / P_DEN[m]) <= 0.5 + 1e-9
