@@ -327,7 +327,7 @@ def measure_filter(emt, torch, raws, calls: int = 20) -> dict:
 
 
 def measure_module(emt, seed: int = 0, calls: int = 3) -> dict:
-    """The efficiency and fake-rate method of Sec. 4 on a synthetic module
+    """The efficiency and fake-rate method of Sec. 3 on a synthetic module
     of four layers, each scanned in 8 x 8 views of 300 x 250 um: all 256
     views tracked in calls of 64 (host arrays, as a microscope hands them
     over), then the layers' tracks matched on the host."""

@@ -85,7 +85,7 @@ extern "C" {
  *               grains, theta the angle of the seed pair to the z axis
  *               (tan = sqrt(dx^2 + dy^2) / |dz|), in both threshold steps;
  *               after the paper's grain-count cut against track angle
- *               (Sec. 4, Fig. 9c). num 0 (default): the threshold is n_min.
+ *               (Sec. 3, Fig. 8c). num 0 (default): the threshold is n_min.
  *               num 0..1024, den 1..1024.
  *   thr_max     cap of that threshold (0: none; else n_min..2^20-1); a seed
  *               with dz = 0 needs the cap (no cap: it is never a track).
@@ -124,7 +124,8 @@ typedef struct {
  * t_end: extent of the grains along dir about the centroid, um.
  * fit_fp64: 1 if the slopes were solved in FP64 (axis == z or RMS spread
  * along axis < 5 um or EMT_F_FP64_FIT_ALWAYS); degenerate: 1 if all grains
- * of the track coincide (dir is then the seed direction). */
+ * of the track coincide (no spread to fit: axis, slopes and dir are then
+ * those of the seed direction g_j - g_i, slopes in FP64, fit_fp64 = 1). */
 typedef struct {
     uint32_t seed[2];
     uint32_t grain_offset;

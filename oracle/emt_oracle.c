@@ -141,8 +141,8 @@ static int on_line(const int32_t *xyz, uint32_t i, const int64_t d[3],
 }
 
 /* Acceptance variant (grain-count threshold rising with the angle; paper
- * Sec. 4: a cut on the number of grains along a line in the plane of grain
- * count against track angle, Fig. 9c). For seed direction d, with
+ * Sec. 3: a cut on the number of grains along a line in the plane of grain
+ * count against track angle, Fig. 8c). For seed direction d, with
  * tan(theta) = sqrt(d_x^2 + d_y^2) / |d_z| and b = thr_num / thr_den, the
  * threshold is the smallest integer m >= n_min with m - n_min >= b tan(theta),
  * capped at thr_max (if set). Tested exactly, squared in 128-bit integers:
@@ -348,7 +348,9 @@ static void fit_track(const int32_t *xyz, uint32_t i, uint32_t j,
         c = (a == 2) ? 1 : 2;
         T->slope[0] = (double)d[b] / (double)d[a];
         T->slope[1] = (double)d[c] / (double)d[a];
-        for (int u = 0; u < 3; u++) comp[u] = d[u];
+        /* (1, slope0, slope1) on axes (a, b, c) is d / d_a: its signs are
+         * those of d times the sign of d_a */
+        for (int u = 0; u < 3; u++) comp[u] = d[a] < 0 ? -d[u] : d[u];
         T->degenerate = 1;
     } else {
         T->slope[0] = C[a][b] / C[a][a];

@@ -12,7 +12,7 @@
  *   count      grains within r of the infinite line through the pair (Fig. 4b)
  *              (variant: of a finite cylinder around the pair)
  *   threshold  keep seeds with at least n_min grains (variant: a threshold
- *              rising with the seed's angle to the z axis, Sec. 4, Fig. 9c)
+ *              rising with the seed's angle to the z axis, Sec. 3, Fig. 8c)
  *   associate  each grain used by one track only, then the threshold again
  *   fit        least-squares direction of each accepted track (FP64)
  *

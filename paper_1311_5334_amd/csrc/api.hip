@@ -16,6 +16,7 @@
 #include <new>
 #include <vector>
 
+#include "capacity.h"
 #include "cell_table.h"
 #include "emt_dev.h"
 #include "emt_host.h"
@@ -30,8 +31,6 @@ constexpr uint32_t kKnownFlags = EMT_F_STATS | EMT_F_FP64_FIT_ALWAYS | EMT_F_DEV
 // paper's 7.5 um hash cell across it.
 constexpr int kDefaultCell[3] = {250, 750, 500};
 constexpr int kMaxAttempts = 4;
-// seeds of one call are indexed by uint32 and scanned in uint32
-constexpr unsigned long long kSeedCapMax = (1ull << 31) - 1;
 
 struct DevArena {
     void *p = nullptr;
@@ -392,12 +391,6 @@ void record(emt_ctx *ctx, int i) {
     if (ctx->cfg.flags & EMT_F_STATS) (void)hipEventRecord(ctx->ev[i], ctx->stream);
 }
 
-uint32_t clamp_u32(double x) {
-    if (x < 1024.0) return 1024u;
-    if (x > 2147483647.0) return 2147483647u;
-    return (uint32_t)x;
-}
-
 // The kernel sequence of one batch, in stages: 0 bin, 1 seeds, 2 count,
 // 3 candidates and members, 4 merge, 5 fit, 6 results to the host; -1 runs
 // them all.
@@ -539,7 +532,9 @@ int run_check(emt_ctx *ctx, const Caps &c, bool *overflow) {
     *overflow = false;
     HIP_OK(hipEventSynchronize(ctx->done));
     const Counters &h = *ctx->h.cnt;
-    if (h.n_seeds > c.seed_cap || h.n_cand > c.cand_cap || h.n_members > c.mem_cap) {
+    const Needs need{h.seeds64, h.members64, h.n_cand};
+    const CapSizes have{c.seed_cap, c.cand_cap, c.mem_cap};
+    if (!fits(need, have)) {
         *overflow = true;
         return EMT_EOVERFLOW;
     }
@@ -590,8 +585,8 @@ int batch_caps(const emt_ctx *ctx, unsigned long long n_total, uint32_t n_views,
     c.seed_cap = std::min<unsigned long long>(
         kSeedCapMax, std::max<unsigned long long>(
                          4096, (unsigned long long)(ctx->seeds_per_grain * (double)c.n_total)));
-    c.cand_cap = clamp_u32(ctx->cand_per_grain * (double)c.n_total);
-    c.mem_cap = clamp_u32(ctx->mem_per_cand * (double)c.cand_cap);
+    c.cand_cap = clamp_cap(ctx->cand_per_grain * (double)c.n_total);
+    c.mem_cap = clamp_cap(ctx->mem_per_cand * (double)c.cand_cap);
     c.wide_rounds = ctx->next_wide > 0 ? ctx->next_wide : max_wide_rounds();
     *out = c;
     return EMT_OK;
@@ -803,24 +798,16 @@ int finish_views(emt_ctx *ctx, emt_view_out *out) {
         if (attempt + 1 >= kMaxAttempts) return EMT_EOVERFLOW;
         ++retries;
         const Counters h = *ctx->h.cnt;
-        // the counters are exact for the stage that overflowed; later stages
-        // are sized from the per-grain and per-candidate ratios
-        if (h.n_seeds > c.seed_cap) {
-            if (h.n_seeds >= kSeedCapMax) return EMT_EOVERFLOW;
-            c.seed_cap = std::min<unsigned long long>(kSeedCapMax,
-                                                      h.n_seeds + h.n_seeds / 8 + 1024);
-            ctx->seeds_per_grain = std::max(ctx->seeds_per_grain, 1.125 * (double)h.n_seeds / std::max(1.0, (double)c.n_total));
-        }
-        if (h.n_cand > c.cand_cap) {
-            c.cand_cap = clamp_u32((double)h.n_cand * 1.125 + 1024);
-            ctx->cand_per_grain = std::max(ctx->cand_per_grain, 1.125 * (double)h.n_cand / std::max(1.0, (double)c.n_total));
-        }
-        if (h.n_members > c.mem_cap || h.n_cand > c.cand_cap) {
-            const double per = h.n_cand ? (double)h.n_members / (double)h.n_cand : ctx->mem_per_cand;
-            ctx->mem_per_cand = std::max(ctx->mem_per_cand, 1.125 * per);
-            c.mem_cap = clamp_u32(std::max((double)h.n_members * 1.125 + 1024,
-                                           ctx->mem_per_cand * (double)c.cand_cap));
-        }
+        const Needs need{h.seeds64, h.members64, h.n_cand};
+        CapSizes next{c.seed_cap, c.cand_cap, c.mem_cap};
+        Ratios ratios{ctx->seeds_per_grain, ctx->cand_per_grain, ctx->mem_per_cand};
+        if (!plan_retry(need, c.n_total, next, ratios)) return EMT_EOVERFLOW;
+        c.seed_cap = next.seed_cap;
+        c.cand_cap = next.cand_cap;
+        c.mem_cap = next.mem_cap;
+        ctx->seeds_per_grain = ratios.seeds_per_grain;
+        ctx->cand_per_grain = ratios.cand_per_grain;
+        ctx->mem_per_cand = ratios.mem_per_cand;
         if ((rc = ensure(ctx, c))) return rc;
         fill_grids(ctx, views, n_views);
         if ((rc = run_launch(ctx, views, n_views, c))) return rc;
@@ -859,7 +846,7 @@ int finish_views(emt_ctx *ctx, emt_view_out *out) {
     ctx->next_wide = std::max(6, std::min(max_wide_rounds(), (int)h.rounds + 2));
     emt_call_stats &st = ctx->last;
     st = emt_call_stats{};
-    st.n_seeds = h.n_seeds;
+    st.n_seeds = h.seeds64;
     st.n_tests = h.tests;
     st.n_hits = h.hits;
     st.n_candidates = h.n_cand;

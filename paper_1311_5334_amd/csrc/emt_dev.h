@@ -62,9 +62,12 @@ struct Params {
 
 // Device counters of one call. Totals keep counting past capacities so the
 // host learns what a retry needs.
+// Seed and member totals come from uint32 scans; their exact 64-bit sums are
+// kept beside them, and a scan total that wrapped is saturated to 2^32 - 1,
+// so a wrapped total always reads as an overflow.
 struct Counters {
     uint32_t n_seeds;
-    uint32_t pad0;
+    uint32_t n_seeds_ok;  // seeds the later stages take: n_seeds if it fits, else 0
     unsigned long long tests;
     unsigned long long hits;
     uint32_t n_cand;
@@ -75,7 +78,9 @@ struct Counters {
     uint32_t rounds;
     uint32_t n_fp64;
     uint32_t err;
-    uint32_t pad[3];
+    uint32_t pad1;
+    unsigned long long seeds64;    // exact number of seeds
+    unsigned long long members64;  // exact number of member entries
 };
 
 struct Cand {

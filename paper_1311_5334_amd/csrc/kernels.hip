@@ -672,6 +672,9 @@ __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
     const int R1 = P.R - 1;
     const int R2 = P.R * P.R;
     const uint32_t n_total = d.desc->n_total;
+    // the write pass has nothing to do when the seeds overflow their buffer
+    if (kWrite && d.cnt->n_seeds_ok == 0) return;
+    unsigned long long wave_total = 0;  // count pass: seeds of this wave's anchors
     for (uint32_t p = gw; p < n_total; p += nw) {
         const uint32_t v = d.view_of[p];
         const ViewGrid *G = &d.grids[v];
@@ -735,8 +738,30 @@ __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
         if (!kWrite) {
             mine = wave_sum(mine);
             if (lane == 0) d.seed_cnt[p] = mine;
+            wave_total += mine;
         }
     }
+    if (!kWrite && lane == 0 && wave_total) atomicAdd(&d.cnt->seeds64, wave_total);
+}
+
+// The seed total of the uint32 scan, replaced by the exact 64-bit count
+// (saturated to 2^32 - 1), and the number of seeds the later stages take:
+// none when they do not fit the seed buffer (the host then re-runs the call
+// with a larger one, or fails if no buffer can hold them).
+__global__ void k_seed_total(Counters *cnt, unsigned long long seed_cap) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const unsigned long long s = cnt->seeds64;
+    const uint32_t n = s > 0xffffffffull ? 0xffffffffu : (uint32_t)s;
+    cnt->n_seeds = n;
+    cnt->n_seeds_ok = n <= seed_cap ? n : 0u;
+}
+
+// Likewise for the member entries (the scan of candidate counts): a total
+// that wrapped reads as an overflow, so no stage uses the wrapped offsets.
+__global__ void k_member_total(Counters *cnt) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const unsigned long long m = cnt->members64;
+    cnt->n_members = m > 0xffffffffull ? 0xffffffffu : (uint32_t)m;
 }
 
 
@@ -845,7 +870,9 @@ __global__ void __launch_bounds__(kBlock) k_members(DevPtrs d, Caps c, Params P)
     constexpr int kItems = 64 / kPer;
     QueueLds<kFinite> &Q = sQ[threadIdx.x >> 6];
     const uint32_t nc = d.cnt->n_cand;
-    const unsigned long long n_items = d.cnt->err ? 0ull : (nc < c.cand_cap ? nc : c.cand_cap);
+    // nothing to list when the entries overflow their buffer (the call is re-run)
+    const bool skip = d.cnt->err || d.cnt->n_members > c.mem_cap;
+    const unsigned long long n_items = skip ? 0ull : (nc < c.cand_cap ? nc : c.cand_cap);
     if (lane < kMaskWords) Q.mask[lane] = 0ull;
     wave_lds_sync();
     const unsigned long long gw = grid_tid() >> 6, nw = grid_threads() >> 6;
@@ -1020,8 +1047,7 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
     __shared__ CountLds<kFinite> sQ[kWaves];
     const int lane = lane_id();
     CountLds<kFinite> &Q = sQ[threadIdx.x >> 6];
-    const unsigned long long ns = d.cnt->n_seeds;
-    const uint32_t n_items = (uint32_t)(ns < c.seed_cap ? ns : c.seed_cap);
+    const uint32_t n_items = d.cnt->n_seeds_ok;
     if (lane < kCountMaskWords) Q.mask[lane] = 0ull;
     wave_lds_sync();
     unsigned long long tests = 0, hits = 0;
@@ -1193,18 +1219,20 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
 // view, from the offsets (views are contiguous in anchor order, so in seed
 // and in candidate order too).
 __global__ void __launch_bounds__(kBlock) k_cand_scatter(DevPtrs d, Caps c, Params P) {
-    const uint32_t ns = min(d.cnt->n_seeds, (uint32_t)c.seed_cap);
+    const uint32_t ns = d.cnt->n_seeds_ok;
     for (uint32_t v = grid_tid(); v < d.desc->n_views; v += grid_threads()) {
         const uint32_t g0 = d.grids[v].grain_off, g1 = g0 + d.grids[v].n;
         const uint32_t s0 = d.seed_off[g0], s1 = d.seed_off[g1];
         d.view_seeds[v] = s1 - s0;
         d.view_cand[v] = d.cand_pos[min(s1, ns)] - d.cand_pos[min(s0, ns)];
     }
+    unsigned long long listed = 0;  // member entries of the listed candidates
     for (uint32_t s = grid_tid(); s < ns; s += grid_threads()) {
         const uint32_t n = d.seed_n[s];
         if (!n) continue;
         const uint32_t pos = d.cand_pos[s];
         if (pos >= c.cand_cap) continue;
+        listed += n;
         const uint2 pq = d.seeds[s];
         Cand cd;
         cd.p = pq.x;
@@ -1217,6 +1245,8 @@ __global__ void __launch_bounds__(kBlock) k_cand_scatter(DevPtrs d, Caps c, Para
         if (P.thr_num) d.cand_thr[pos] = seed_threshold(gj.x - gi.x, gj.y - gi.y, gj.z - gi.z, P);
         d.key[pos] = cand_key(n, (uint32_t)gi.w, (uint32_t)gj.w);
     }
+    listed = wave_sum(listed);
+    if (lane_id() == 0 && listed) atomicAdd(&d.cnt->members64, listed);
 }
 
 // The threshold a candidate's unused grains must reach: n_min, or its own
@@ -1677,24 +1707,35 @@ __global__ void __launch_bounds__(kBlock) k_fit(DevPtrs d, Params P) {
         float slope[2];
         int comp_sign[3];
         uint32_t fp64 = 0, degen = 0;
+        double s0d = 0.0, s1d = 0.0;  // slopes of the FP64 paths
         if (Q[a][a] == 0) {
+            // every grain coincides: no spread to fit, the seed direction
+            // stands in (its spread along any axis is 0, under the 5 um
+            // rule, so the ratio is taken in FP64)
             degen = 1;
+            fp64 = 1;
             const int ad[3] = {dx, dy, dz};
             a = 0;
             if (abs(ad[1]) > abs(ad[a])) a = 1;
             if (abs(ad[2]) > abs(ad[a])) a = 2;
             b = a == 0 ? 1 : 0;
             cx = a == 2 ? 1 : 2;
-            slope[0] = (float)ad[b] / (float)ad[a];
-            slope[1] = (float)ad[cx] / (float)ad[a];
-            for (int u = 0; u < 3; ++u) comp_sign[u] = ad[u] > 0 ? 1 : (ad[u] < 0 ? -1 : 0);
+            s0d = (double)ad[b] / (double)ad[a];
+            s1d = (double)ad[cx] / (double)ad[a];
+            slope[0] = (float)s0d;
+            slope[1] = (float)s1d;
+            // (1, slope) on axes (a, b, c) is d / d_a: signs of d times that of d_a
+            const int sa = ad[a] < 0 ? -1 : 1;
+            for (int u = 0; u < 3; ++u) comp_sign[u] = sa * (ad[u] > 0 ? 1 : (ad[u] < 0 ? -1 : 0));
         } else {
             fp64 = (a == 2) || (Q[a][a] < (__int128)250000 * n * n) ||
                    (P.flags & EMT_F_FP64_FIT_ALWAYS) != 0;
             if (fp64) {
                 const double qa = i128_to_f64(Q[a][a]);
-                slope[0] = (float)(i128_to_f64(Q[a][b]) / qa);
-                slope[1] = (float)(i128_to_f64(Q[a][cx]) / qa);
+                s0d = i128_to_f64(Q[a][b]) / qa;
+                s1d = i128_to_f64(Q[a][cx]) / qa;
+                slope[0] = (float)s0d;
+                slope[1] = (float)s1d;
             } else {
                 const float qa = i128_to_f32(Q[a][a]);
                 slope[0] = i128_to_f32(Q[a][b]) / qa;
@@ -1706,10 +1747,6 @@ __global__ void __launch_bounds__(kBlock) k_fit(DevPtrs d, Params P) {
         }
         {
             if (fp64) {
-                // fp64 is only set for a non-degenerate fit
-                const double qa = i128_to_f64(Q[a][a]);
-                const double s0d = i128_to_f64(Q[a][b]) / qa;
-                const double s1d = i128_to_f64(Q[a][cx]) / qa;
                 const double nrm = sqrt(1.0 + s0d * s0d + s1d * s1d);
                 dir[a] = (float)(1.0 / nrm);
                 dir[b] = (float)(s0d / nrm);
@@ -2224,7 +2261,9 @@ void launch_seeds(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t 
     const uint32_t nb = blocks_for(64ull * c.n_total, 4 * kPersistentBlocks);
     k_seeds<false><<<nb, kBlock, 0, s>>>(d, c, P);
     // the scan total counts every seed (it wraps only above 2^32 - 1 a call)
+    // offsets in uint32: exact whenever the total fits, which k_seed_total checks
     scan_excl(d.seed_cnt, &d.desc->n_total, c.n_total, d.scan_part, d.seed_off, &d.cnt->n_seeds, s);
+    k_seed_total<<<1, 64, 0, s>>>(d.cnt, c.seed_cap);
     k_seeds<true><<<nb, kBlock, 0, s>>>(d, c, P);
 }
 
@@ -2236,13 +2275,14 @@ void launch_count(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t 
 }
 
 void launch_candidates(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
-    scan_excl<true>(d.seed_n, &d.cnt->n_seeds, (uint32_t)c.seed_cap, d.scan_part, d.cand_pos,
+    scan_excl<true>(d.seed_n, &d.cnt->n_seeds_ok, (uint32_t)c.seed_cap, d.scan_part, d.cand_pos,
                     &d.cnt->n_cand, s);
     k_cand_scatter<<<blocks_for(c.seed_cap, kPersistentBlocks), kBlock, 0, s>>>(d, c, P);
 }
 
 void launch_members(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
     scan_excl(d.cand_n, &d.cnt->n_cand, c.cand_cap, d.scan_part, d.mem_off, &d.cnt->n_members, s);
+    k_member_total<<<1, 64, 0, s>>>(d.cnt);
     const uint32_t nb =
         blocks_for((unsigned long long)EMT_MEMBER_LANES * c.cand_cap, kPersistentBlocks);
     if (P.cyl_ext >= 0)

@@ -300,19 +300,22 @@ int emt_server_submit(emt_server *S, const emt_view_in *view, uint64_t *ticket) 
     }
     r->n = view->n_grains;
     r->view_id = view->view_id;
+    uint64_t my_ticket;
     {
         std::lock_guard<std::mutex> g(S->mu);
         if (S->fatal || S->stop) {
             delete r;
             return S->fatal ? S->fatal : EMT_EINVAL;
         }
-        r->ticket = S->next_ticket++;
+        // the request belongs to the worker once queued: keep what is
+        // reported from it before the lock is released
+        my_ticket = r->ticket = S->next_ticket++;
         r->t_submit = now_ms(S);
         S->queue.push_back(r);
         S->st.submitted++;
     }
     S->cv_work.notify_one();
-    if (ticket) *ticket = r->ticket;
+    if (ticket) *ticket = my_ticket;
     return EMT_OK;
 }
 

@@ -1,21 +1,21 @@
 """A synthetic emulsion module and the paper's efficiency and fake-rate
-method (Sec. 4; Fig. 9, Fig. 10): a second workload for the unchanged
+method (Sec. 3; Fig. 8, Fig. 9): a second workload for the unchanged
 tracking path.
 
-Module (Sec. 4): a detector is a 200 um plastic base with a 50 um emulsion
+Module (Sec. 3): a detector is a 200 um plastic base with a 50 um emulsion
 layer on each side; two detectors are stacked, giving four sensitive layers
 at z = 0-50, 250-300, 300-350 and 550-600 um (the detectors are taken to
 touch, and to be perfectly aligned). It is exposed to cosmic rays: straight
 lines through the whole module, crossing a horizontal plane with a cos^3
 distribution of the zenith angle (a cos^2 flux per solid angle, seen
 through the plane) up to a maximum tan(theta). A MIP leaves 42 grains per
-100 um of emulsion (Sec. 4). Low-energy electrons add short random tracks,
+100 um of emulsion (Sec. 3). Low-energy electrons add short random tracks,
 and fog fills every layer. Each layer is scanned in views of 300 x 250 um
 (Sec. 2) tiling the module; every view is tracked on its own, in its own
 coordinates (0.01 um units from the view's corner), so a track crossing a
 view edge is cut in two as on the microscope.
 
-Method (Sec. 4, Fig. 10 left): tracks found in layers 0, 1 and 3 that line
+Method (Sec. 3, Fig. 9 left): tracks found in layers 0, 1 and 3 that line
 up are joined into one reference line; its prediction in layer 2 is
 searched for among layer 2's tracks; the fraction found is the efficiency,
 per bin of the zenith angle. The fake rate is the same search with the data

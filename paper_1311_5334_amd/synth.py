@@ -310,3 +310,21 @@ def make_tiny_tracks(seed: int, n_tracks: int, n_fog: int, side_um: float,
     _ = vol
     return View(to_units(pts[perm]).reshape(-1, 3), lab[perm],
                 (float(box[0]), float(box[1])), [], "tiny", seed)
+
+
+def make_degenerate_view(p=(20000, 20000, 2000), q_offset=(1000, 0, 0),
+                         delta=(0, 300, 100), n_copies: int = 8, n_line: int = 11,
+                         shift: int = 0) -> np.ndarray:
+    """Units, int32: n_copies grains at one point P (indices 0 .. n_copies-1),
+    then n_line grains on a lattice line through Q = P + q_offset with step
+    delta, which does not pass near P. The line's seeds outrank every seed
+    through P, so it takes Q and its neighbours first; a seed through P is
+    then left with the coincident copies only, which have no spread to fit.
+    shift moves the line along itself by that many steps."""
+    P = np.asarray(p, np.int64)
+    Q = P + np.asarray(q_offset, np.int64)
+    D = np.asarray(delta, np.int64)
+    half = n_line // 2
+    line = [Q + (m + shift) * D for m in range(-half, n_line - half)]
+    return np.concatenate([np.repeat(P[None, :], n_copies, axis=0),
+                           np.array(line, np.int64)]).astype(np.int32)

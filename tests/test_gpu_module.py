@@ -1,4 +1,4 @@
-"""The module workload on the GPU (paper, Sec. 4): every view of a small
+"""The module workload on the GPU (paper, Sec. 3): every view of a small
 module tracked in one batched call matches the oracle view by view, and the
 efficiency and fake-rate method gives the same counts on both track sets;
 on a full module the tracking efficiency is high and the fake rate low."""

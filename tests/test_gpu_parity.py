@@ -379,3 +379,43 @@ def test_stats_time_every_stage(emt):
         st = tr.stats()
     assert all(ms > 0 for ms in st["ms"].values()), st["ms"]
     assert st["n_tests"] > 0 and st["n_seeds"] > 0
+
+
+@pytest.mark.parametrize("q_offset,delta", [((1000, 0, 0), (0, 300, 100)),
+                                            ((0, -900, 300), (250, 0, 0)),
+                                            ((0, 0, -1200), (170, -170, 0)),
+                                            ((-700, 700, 0), (0, 0, 170))])
+def test_degenerate_fit_matches_oracle(tracker, oracle_mod, q_offset, delta):
+    """A track left with coincident grains only takes the seed direction
+    (the fit's degenerate branch), alone and inside a batch."""
+    xyz = synth.make_degenerate_view(q_offset=q_offset, delta=delta)
+    ref = oracle_mod.track_view(xyz)
+    assert [t["degenerate"] for t in ref.tracks] == [0, 1]
+    got = run1(tracker, xyz)
+    assert_view_parity(xyz, got, ref)
+    assert int(got["tracks"][1]["degenerate"]) == 1
+    other = synth.make_c1(2).xyz
+    batch = tracker([other, xyz, xyz[::-1].copy()])
+    assert_view_parity(xyz, batch[1], ref)
+    assert_view_parity(xyz[::-1].copy(), batch[2], oracle_mod.track_view(xyz[::-1].copy()))
+
+
+def test_seed_total_above_2_32_is_an_overflow(emt):
+    """96,000 grains in a 14 um cube: every pair is a seed, 4.6e9 in all,
+    more than a uint32 scan holds. The call must fail with EMT_EOVERFLOW
+    (the wrapped total would otherwise look like a small, fitting one), and
+    the context must stay usable."""
+    rng = np.random.default_rng(20250)
+    n = 96000
+    xyz = (rng.integers(0, 1400, size=(n, 3)) + 50000).astype(np.int32)
+    assert n * (n - 1) // 2 > (1 << 32) + (1 << 28)
+    _say(f"dense cube: {n} grains, {n * (n - 1) // 2} pairs")
+    with emt.Tracker(device=0) as t:
+        with pytest.raises(emt.EmtError) as e:
+            t([xyz])
+        assert e.value.rc == emt.EMT_EOVERFLOW
+        small = synth.make_c1(3).xyz
+        again = t([small])[0]
+    with emt.Tracker(device=0) as t2:
+        ref = t2([small])[0]
+    assert again["tracks"].tobytes() == ref["tracks"].tobytes()

@@ -1,6 +1,6 @@
 """The acceptance variants on the GPU against the oracle: the paper's own
 threshold n > 5 (n_min = 6), finite cylinders and the angle-dependent
-grain-count threshold (Sec. 4, Fig. 9c), alone and together, on single
+grain-count threshold (Sec. 3, Fig. 8c), alone and together, on single
 views and in a batched call."""
 import sys
 

@@ -1,5 +1,5 @@
-"""The module workload and the efficiency / fake-rate method (paper, Sec. 4;
-Fig. 9, 10) on the host: module geometry and cosmic-ray angles, and the
+"""The module workload and the efficiency / fake-rate method (paper, Sec. 3;
+Fig. 8, 9) on the host: module geometry and cosmic-ray angles, and the
 method's matching pinned with exact track lists made from the generated
 lines (every crossing found, none found, displaced data)."""
 import numpy as np

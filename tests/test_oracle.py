@@ -282,20 +282,61 @@ def test_fit_slopes_match_exact_rationals(oracle_mod):
             assert t["t_end"] == pytest.approx(proj.max(), abs=1e-9)
 
 
-def test_fit_of_all_coincident_members_is_flagged_degenerate(oracle_mod):
-    # 8 copies of one grain plus a seed partner: the only track keeps the seed
-    # direction because its members have no spread along any axis
+def test_eight_grains_with_their_partner_are_an_ordinary_track(oracle_mod):
+    # 8 copies of one grain plus a seed partner: the partner gives the track
+    # a spread, so it is fitted as usual (not degenerate)
     pts = [[20000, 20000, 2000]] * NMIN + [[20300, 20400, 2000]]
-    xyz = np.array(pts, np.int32)
-    res = oracle_mod.track_view(xyz)
+    res = oracle_mod.track_view(np.array(pts, np.int32))
     assert len(res.tracks) == 1
     t = res.tracks[0]
     assert t["n_grains"] == NMIN + 1 and t["degenerate"] == 0
-    # now hide the partner in a longer track so only the copies remain
-    line = lattice((20000 - 300 * 5, 20000 - 400 * 5, 2000), (300, 400, 0), 12)
-    xyz2 = np.concatenate([line, np.array([[20000, 20000, 2000]] * NMIN)]).astype(np.int32)
-    res2 = oracle_mod.track_view(xyz2)
-    assert len(res2.tracks) == 1
+
+
+def _canonical(v):
+    v = np.asarray(v, np.float64)
+    if v[2] != 0:
+        s = v[2] < 0
+    elif v[1] != 0:
+        s = v[1] < 0
+    else:
+        s = v[0] < 0
+    return -v if s else v
+
+
+@pytest.mark.parametrize("q_offset,delta", [((1000, 0, 0), (0, 300, 100)),
+                                            ((0, -900, 300), (250, 0, 0)),
+                                            ((0, 0, -1200), (170, -170, 0)),
+                                            ((-700, 700, 0), (0, 0, 170))])
+def test_fit_of_all_coincident_members_is_degenerate(oracle_mod, q_offset, delta):
+    # 8 copies at P and a lattice line through a partner Q: the line's seeds
+    # (11 grains) outrank every seed through P (the copies, the partner and
+    # at most a few line grains), take their grains first, and leave the best
+    # seed through P with the 8 coincident copies only
+    xyz = synth.make_degenerate_view(q_offset=q_offset, delta=delta)
+    assert_same_as_brute(oracle_mod, xyz)
+    res = oracle_mod.track_view(xyz)
+    assert len(res.tracks) == 2
+    line = set(range(NMIN, len(xyz)))
+    assert set(res.track_grains(0).tolist()) == line
+    assert res.tracks[0]["degenerate"] == 0
+    t = res.tracks[1]
+    assert t["degenerate"] == 1
+    assert res.track_grains(1).tolist() == list(range(NMIN))
+    i, j = t["i"], t["j"]
+    assert i < NMIN <= j  # a copy of P and a grain of the line
+    d = xyz[j].astype(np.int64) - xyz[i].astype(np.int64)
+    a = int(np.argmax(np.abs(d)))  # ties to the lowest axis
+    b, c = [u for u in range(3) if u != a]
+    assert t["axis"] == a
+    # slopes are the seed's own ratios, correctly rounded
+    assert t["slope"][0] == float(Fraction(int(d[b]), int(d[a])))
+    assert t["slope"][1] == float(Fraction(int(d[c]), int(d[a])))
+    want = _canonical(d / np.linalg.norm(d))
+    assert np.allclose(t["dir"], want, rtol=0, atol=1e-15)
+    # no spread: FP64 by the 5 um rule, extent zero, centroid at P
+    assert t["fit_fp64"] == 1
+    assert t["t_begin"] == 0.0 and t["t_end"] == 0.0
+    assert np.allclose(t["centroid"], xyz[0] / 100.0, rtol=0, atol=1e-12)
 
 
 # --------------------------------------------------------- statistics (MC)

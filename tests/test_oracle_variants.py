@@ -1,7 +1,7 @@
 """Pins of the oracle's acceptance variants: the finite cylinder around a
 seed (instead of the infinite line of the tracking paragraph of Sec. 2) and
-the grain-count threshold rising with the track angle (Sec. 4, the cut of
-Fig. 9c), against closed forms on lattice tracks, an independent brute
+the grain-count threshold rising with the track angle (Sec. 3, the cut of
+Fig. 8c), against closed forms on lattice tracks, an independent brute
 force on tiny views, and exact containment relations."""
 import numpy as np
 import pytest
