@@ -1,16 +1,19 @@
 """Throughput of the 4pi track finder on one MI355X.
 
 One step = one whole pass of the tracking path (bin, seeds, count, members,
-merge, fit, copy-out) over one full view of the c2 workload: 350 x 350 x 50
-um, 300 isotropic tracks (20 % stopping), fog 3 grains per 1000 um^3, about
-27.6k grains. The grains are resident in HBM before the timed region starts
-(device-pointer input); results are copied back to the host inside it.
+merge, fit, copy-out) over one batch of the largest single-GPU workload: 32
+dense star-topology views per call (350 x 350 x 50 um each, 10 vertices of
+3-8 prongs, 200 tracks, fog 10 grains per 1000 um^3, about 70k grains a
+view), all through one sequence of launches. The grains are resident in HBM
+before the timed region starts (device-pointer input); results are copied
+back to the host inside it.
 
-Prints one JSON line: grains/s (value), mm^2/hour, view latency p50/p99, the
-counting kernel's roofline (HIP events on the library's stream), and the
-CPU oracle timed on one view on this host. The same line carries the
-batched form: 64 uneven c3 views per call and 32 dense c5 views per call,
-each through one sequence of launches.
+Prints one JSON line: grains/s (value), mm^2/hour, per-call latency p50/p99,
+the counting kernel's roofline (HIP events on the library's stream) and the
+binning stage's HBM rate, and the CPU oracle timed on this host (one core and
+the whole box). The same line carries the other forms: the plain path on one
+c2 view, 64 uneven c3 views per call, the served c4 stream, grain
+recognition, filtering, the module workload and the acceptance variants.
 """
 from __future__ import annotations
 
@@ -85,24 +88,88 @@ def valu_counters_for_current_kernel():
     return {k: rec[k] for k in ("valu_issue_frac", "lane_util", "lane_ops_frac_of_peak")}
 
 
-def cpu_baseline(first_index: int, min_seconds: float = 10.0, max_views: int = 3):
-    """The oracle, single-threaded on a host core, on the benchmark view and
-    the next seeded c2 views until about min_seconds of work (at most
-    max_views views): grains per second of oracle time."""
-    from oracle import oracle
+def _lscpu() -> dict:
+    """Host CPU model and core counts as lscpu reports them."""
+    import subprocess
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+    except (OSError, subprocess.SubprocessError):
+        txt = ""
+    f = {}
+    for line in txt.splitlines():
+        if ":" in line:
+            k, v = line.split(":", 1)
+            f[k.strip()] = v.strip()
+
+    def num(key, default):
+        try:
+            return int(f.get(key, default))
+        except ValueError:
+            return default
+    cpus = num("CPU(s)", os.cpu_count() or 1)
+    tpc = max(1, num("Thread(s) per core", 1))
+    per_socket = num("Core(s) per socket", 0)
+    physical = per_socket * max(1, num("Socket(s)", 1)) if per_socket else max(1, cpus // tpc)
+    return {"model": f.get("Model name", "unknown"), "physical_cores": physical,
+            "logical_cpus": cpus, "threads_per_core": tpc}
+
+
+def c5_quarter(view_index: int, quarter: int) -> np.ndarray:
+    """One quarter (175 x 175 um) of a c5 view: a bounded sample of the
+    benchmark workload for the CPU oracle."""
     from paper_1311_5334_amd import synth
+    x = synth.make_c5(view_index).xyz
+    qx, qy = quarter % 2, quarter // 2
+    keep = ((x[:, 0] >= qx * 17500) & (x[:, 0] < (qx + 1) * 17500) &
+            (x[:, 1] >= qy * 17500) & (x[:, 1] < (qy + 1) * 17500))
+    return np.ascontiguousarray(x[keep])
+
+
+def _oracle_crop_worker(view_index: int, quarter: int) -> None:
+    """Child-process mode: time the oracle on one c5 quarter, print JSON."""
+    from oracle import oracle
+    xyz = c5_quarter(view_index, quarter)
+    t0 = time.perf_counter()
+    oracle.track_view(xyz)
+    dt = time.perf_counter() - t0
+    print(json.dumps({"grains": int(len(xyz)), "seconds": dt}), flush=True)
+
+
+def cpu_baseline() -> dict:
+    """The oracle (single-threaded C, as it stands) on quarters of c5 views,
+    timed on this host before the GPU is touched: one process on one core,
+    then P processes at once, P = the physical cores available (at most the
+    cores this process may run on), each on its own quarter."""
+    import subprocess
+    from oracle import oracle
     oracle.build()
-    grains, spent, n_views = 0, 0.0, 0
-    while n_views < max_views and (n_views == 0 or spent < min_seconds):
-        v = synth.make_c2(first_index + n_views)
+    info = _lscpu()
+    allowed = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else info["logical_cpus"]
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    P = max(1, min(info["physical_cores"], allowed, share if share > 0 else allowed))
+
+    def run(jobs):
+        procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-crop",
+                                   str(v), str(q)], stdout=subprocess.PIPE, text=True)
+                 for v, q in jobs]
         t0 = time.perf_counter()
-        oracle.track_view(v.xyz)
-        spent += time.perf_counter() - t0
-        grains += v.n
-        n_views += 1
-    return {"value": grains / spent, "unit": "grains/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_views} c2 views from index {first_index} ({grains} grains), "
-                      f"single-threaded C oracle, {spent:.2f} s"}
+        outs = [json.loads(p.communicate(timeout=600)[0].strip().splitlines()[-1]) for p in procs]
+        return outs, time.perf_counter() - t0
+
+    one, _ = run([(0, 0)])
+    box, box_wall = run([(1 + k // 4, k % 4) for k in range(P)])
+    g1, s1 = one[0]["grains"], one[0]["seconds"]
+    gb = sum(o["grains"] for o in box)
+    slowest = max(o["seconds"] for o in box)
+    return {"value": round(g1 / s1, 1), "unit": "grains/s", "cores": 1, "kind": "oracle",
+            "sample": f"one quarter (175x175 um) of c5 view 0, {g1} grains, "
+                      f"single-threaded C oracle, {s1:.2f} s of tracking",
+            "host": info,
+            "whole_box": {"value": round(gb / slowest, 1), "unit": "grains/s", "cores": P,
+                          "sample": f"{P} processes at once, each on its own quarter of c5 "
+                                    f"views 1..{(P - 1) // 4 + 1} ({gb} grains); rate over the "
+                                    f"slowest process's {slowest:.2f} s of tracking",
+                          "wall_s_with_generation": round(box_wall, 2)}}
 
 
 def measure_batch(emt, torch, views, calls: int, warmup: int) -> dict:
@@ -385,37 +452,116 @@ def measure_variants(emt, torch, view, calls: int = 20) -> dict:
     return out
 
 
+def measure_plain(emt, torch, view, steps: int, warmup: int) -> dict:
+    """The plain path: one c2 view per call, device-resident, with stage
+    events; the same loop without events and with host arrays beside it."""
+    dev = torch.from_numpy(view.xyz).to("cuda:0").contiguous()
+    torch.cuda.synchronize()
+    tr = emt.Tracker(device=0, flags=emt.EMT_F_DEVICE_PTRS | emt.EMT_F_STATS)
+    for _ in range(warmup):
+        tr([dev])
+    torch.cuda.synchronize()
+    lat, stage_ms = [], []
+    stats = None
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        tr([dev])
+        lat.append(time.perf_counter() - t0)
+        stats = tr.stats()
+        stage_ms.append(stats["ms"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    tr.close()
+    # one graph launch per call (no stage events): the library's own rate
+    with emt.Tracker(device=0, flags=emt.EMT_F_DEVICE_PTRS) as tq:
+        for _ in range(3):
+            tq([dev])
+        torch.cuda.synchronize()
+        t_q = time.perf_counter()
+        for _ in range(steps):
+            tq([dev])
+        torch.cuda.synchronize()
+        wall_q = time.perf_counter() - t_q
+    # the view as a host array: PCIe copies of grains and tracks in each call
+    with emt.Tracker(device=0) as th:
+        for _ in range(3):
+            th([view.xyz])
+        h_lat = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            th([view.xyz])
+            h_lat.append(time.perf_counter() - t0)
+    h_lat_ms = np.array(h_lat) * 1e3
+    lat_ms = np.array(lat) * 1e3
+    ms = {k: float(np.mean([st[k] for st in stage_ms])) for k in stage_ms[0]}
+    count_s = ms["count"] * 1e-3
+    if count_s <= 0:
+        raise RuntimeError("the library reported no device time for the counting stage")
+    tests = stats["n_tests"]
+    achieved = tests * OPS_PER_TEST / count_s / 1e12
+    peak = VALU_PEAK_OPS / 1e12
+    return {
+        "workload": "c2: one full 350x350x50 um view per call, 300 tracks, fog 3/1000 um^3",
+        "grains_per_view": view.n,
+        "grains_per_s": round(view.n * steps / wall, 1),
+        "mm2_per_hour": round(view.area_mm2 * steps / wall * 3600.0, 2),
+        "ms_per_view": round(wall / steps * 1e3, 4),
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 4)},
+        "stage_ms": {k: round(v, 4) for k, v in ms.items()},
+        "work": {"seeds": stats["n_seeds"], "tests": tests, "hits": stats["n_hits"],
+                 "tests_per_hit": round(tests / max(1, stats["n_hits"]), 3),
+                 "candidates": stats["n_candidates"], "tracks": stats["n_tracks"],
+                 "merge_rounds": stats["merge_rounds"], "fp64_fits": stats["n_fp64_fits"]},
+        "roofline": {"kernel": "k_count", "bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(peak, 2), "unit": "Tops/s",
+                     "frac": round(achieved / peak, 4)},
+        "without_stage_events": {"grains_per_s": round(view.n * steps / wall_q, 1),
+                                 "ms_per_view": round(wall_q / steps * 1e3, 4)},
+        "host_input": {"grains_per_s": round(view.n / (float(h_lat_ms.mean()) * 1e-3), 1),
+                       "latency_ms": {"p50": round(float(np.percentile(h_lat_ms, 50)), 4),
+                                      "p99": round(float(np.percentile(h_lat_ms, 99)), 4)},
+                       "note": "the c2 view as a host array: PCIe copies of grains and "
+                               "results inside each call"},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--view-index", type=int, default=0)
-    ap.add_argument("--forms", default="c3,c5,c4,stacks,raw,module,variants",
-                    help="other forms to add to the line (comma list of c3, c5 batched, "
-                         "c4 served, stacks for grain recognition, raw for filtering, "
-                         "module for the efficiency method and variants for the acceptance "
-                         "variants; '' for none)")
+    ap.add_argument("--forms", default="c2,c3,c4,stacks,raw,module,variants",
+                    help="other forms to add to the line (comma list of c2 plain, c3 "
+                         "batched, c4 served, stacks for grain recognition, raw for "
+                         "filtering, module for the efficiency method and variants for the "
+                         "acceptance variants; '' for none)")
     ap.add_argument("--served-requests", type=int, default=5000)
     ap.add_argument("--served-warmup", type=int, default=500)
     ap.add_argument("--form-calls", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy, the reference "
                          "for scaling FETCH_SIZE/WRITE_SIZE counters")
+    ap.add_argument("--oracle-crop", nargs=2, type=int, metavar=("VIEW", "QUARTER"),
+                    help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_crop:
+        _oracle_crop_worker(*args.oracle_crop)
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); views are "
               "independent, so N GPUs would each run this same per-GPU workload", file=sys.stderr)
         return 2
 
+    # the CPU oracle first, before anything touches the GPU
+    base = None if args.no_cpu_baseline else cpu_baseline()
+
     import torch
     from paper_1311_5334_amd import emt, synth
 
     assert torch.cuda.is_available(), "bench needs a GPU"
-    view = synth.make_c2(args.view_index)
-    dev = torch.from_numpy(view.xyz).to("cuda:0").contiguous()
-    torch.cuda.synchronize()
     if args.calibrate_copy:
         src = torch.empty(64 << 20, dtype=torch.int32, device="cuda:0").fill_(1)
         dst = torch.empty_like(src)
@@ -423,65 +569,41 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    # the headline: 32 c5 views per call, device-resident, stage events on
+    views = [synth.make_c5(i) for i in range(32)]
+    devs = [torch.from_numpy(v.xyz).to("cuda:0").contiguous() for v in views]
+    grains = sum(v.n for v in views)
+    area = sum(v.area_mm2 for v in views)
+    torch.cuda.synchronize()
     tr = emt.Tracker(device=0, flags=emt.EMT_F_DEVICE_PTRS | emt.EMT_F_STATS)
     for _ in range(args.warmup):
-        tr([dev])
+        tr(devs)
     torch.cuda.synchronize()
-
     lat, stage_ms = [], []
     stats = None
     t_start = time.perf_counter()
     for _ in range(args.steps):
         t0 = time.perf_counter()
-        res = tr([dev])
+        tr(devs)
         lat.append(time.perf_counter() - t0)
-        st = tr.stats()
-        stage_ms.append(st["ms"])
-        stats = st
+        stats = tr.stats()
+        stage_ms.append(stats["ms"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     tr.close()
-
-    # the same loop without per-stage events (one graph launch per call
-    # instead of one per stage): the library's rate when no timing is asked
-    # for; the reported value keeps the events, which time the kernels
-    with emt.Tracker(device=0, flags=emt.EMT_F_DEVICE_PTRS) as tq:
-        for _ in range(3):
-            tq([dev])
-        torch.cuda.synchronize()
-        t_q = time.perf_counter()
-        for _ in range(args.steps):
-            tq([dev])
-        torch.cuda.synchronize()
-        wall_q = time.perf_counter() - t_q
-
-    # the same view handed over as a host array (not the reported value):
-    # each call then includes the PCIe copies of the grains in and the
-    # tracks out
-    with emt.Tracker(device=0) as th:
-        for _ in range(3):
-            th([view.xyz])
-        h_lat = []
-        for _ in range(args.steps):
-            t0 = time.perf_counter()
-            th([view.xyz])
-            h_lat.append(time.perf_counter() - t0)
-    h_lat_ms = np.array(h_lat) * 1e3
-
-    grains = view.n * args.steps
-    value = grains / wall
-    mm2_h = view.area_mm2 * args.steps / wall * 3600.0
     lat_ms = np.array(lat) * 1e3
-    ms = {k: float(np.mean([s[k] for s in stage_ms])) for k in stage_ms[0]}
-    count_s = ms["count"] * 1e-3
+    ms = {k: float(np.mean([st[k] for st in stage_ms])) for k in stage_ms[0]}
+    count_s, bin_s = ms["count"] * 1e-3, ms["bin"] * 1e-3
+    if count_s <= 0 or bin_s <= 0:
+        raise RuntimeError("the library reported no device time for a stage")
     tests = stats["n_tests"]
-    if count_s <= 0:
-        raise RuntimeError("the library reported no device time for the counting stage")
     achieved = tests * OPS_PER_TEST / count_s / 1e12
     peak = VALU_PEAK_OPS / 1e12
+    bin_gbs = BIN_BYTES_PER_GRAIN * grains / bin_s / 1e9
     out = {
-        "metric": "grains/s and mm^2/hour per GPU (plain per-view path); p50/p99 view latency",
-        "value": round(value, 1),
+        "metric": "grains/s and mm^2/hour per GPU, batched+served vs plain; p50/p99 view latency",
+        "value": round(grains * args.steps / wall, 1),
         "unit": "grains/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -492,35 +614,41 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "i32",
         "data": "synthetic",
-        "config": {"workload": "c2: one full 350x350x50 um view, 300 tracks, "
-                               "fog 3/1000 um^3, R=25 um, r=0.5 um, n_min=8",
-                   "grains_per_view": view.n, "form": "plain", "views_per_step": 1},
-        "mm2_per_hour": round(mm2_h, 2),
+        "config": {"workload": "c5 batched: 32 dense views per call, each 350x350x50 um with "
+                               "10 vertices of 3-8 prongs (0.3-1.0 grains/um, 3-200 um), 200 "
+                               "tracks, fog 10/1000 um^3; R=25 um, r=0.5 um, n_min=8",
+                   "form": "batched", "views_per_step": len(views), "grains_per_step": grains},
+        "mm2_per_hour": round(area * args.steps / wall * 3600.0, 2),
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
-                       "p99": round(float(np.percentile(lat_ms, 99)), 4)},
+                       "p99": round(float(np.percentile(lat_ms, 99)), 4),
+                       "note": "per call of 32 views (all views of a call finish together)"},
         "stage_ms": {k: round(v, 4) for k, v in ms.items()},
         "work": {"seeds": stats["n_seeds"], "tests": tests, "hits": stats["n_hits"],
                  "tests_per_hit": round(tests / max(1, stats["n_hits"]), 3),
+                 "tests_per_seed": round(tests / max(1, stats["n_seeds"]), 3),
                  "candidates": stats["n_candidates"], "tracks": stats["n_tracks"],
                  "merge_rounds": stats["merge_rounds"], "fp64_fits": stats["n_fp64_fits"]},
         "roofline": {"kernel": "k_count", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(peak, 2), "unit": "Tops/s",
                      "frac": round(achieved / peak, 4),
                      "traffic": traffic_for_current_kernel(tests),
-                     "counters": valu_counters_for_current_kernel()},
+                     "counters": valu_counters_for_current_kernel(),
+                     "note": "18 integer/FP32 lane operations per (seed, grain) test over "
+                             "k_count's device time from HIP events on the library stream"},
+        "bin_roofline": {"achieved": round(bin_gbs, 1), "unit": "GB/s",
+                         "bytes_per_grain": BIN_BYTES_PER_GRAIN, "peak": HBM_PEAK_GBS,
+                         "frac": round(bin_gbs / HBM_PEAK_GBS, 4)},
     }
     forms = {}
     for f in [x for x in args.forms.split(",") if x]:
-        if f == "c3":
+        if f == "c2":
+            forms["plain_c2"] = measure_plain(emt, torch, synth.make_c2(0), args.steps,
+                                              args.warmup)
+        elif f == "c3":
             vs = [synth.make_c3(i) for i in range(64)]
             forms["batched_c3"] = measure_batch(emt, torch, vs, args.form_calls, 2)
             forms["batched_c3"]["workload"] = ("c3: 64 views per call, 2k-40k grains each "
                                                "(log-uniform), 50-500 tracks, fog 1-5/1000 um^3")
-        elif f == "c5":
-            vs = [synth.make_c5(i) for i in range(32)]
-            forms["batched_c5"] = measure_batch(emt, torch, vs, args.form_calls, 1)
-            forms["batched_c5"]["workload"] = ("c5: 32 views per call, 350x350x50 um, 10 stars "
-                                               "of 3-8 prongs, 200 tracks, fog 10/1000 um^3")
         elif f == "stacks":
             from paper_1311_5334_amd import synth_stack
             sts = [synth_stack.make_stack(i) for i in range(2)]
@@ -544,35 +672,29 @@ def main() -> int:
                 "angles to tan 2.5, fog 3/1000 um^3, 2 electrons a view; layers 0, 1, 3 "
                 "predict layer 2; fakes with layer 2 displaced by 1 mm")
         elif f == "variants":
-            forms["acceptance_variants"] = measure_variants(emt, torch, view)
+            forms["acceptance_variants"] = measure_variants(emt, torch, synth.make_c2(0))
             forms["acceptance_variants"]["workload"] = (
-                "the c2 benchmark view under each acceptance variant; device time of the "
+                "the c2 view under each acceptance variant; device time of the "
                 "whole path per view")
         elif f == "c4":
             vs = [synth.make_c4(i) for i in range(96)]
             forms["served_c4"] = measure_served(emt, vs, args.served_requests, args.served_warmup)
             forms["served_c4"]["workload"] = (
                 "c4: Poisson stream drawn from 96 views of 100^2, 200^2 or 350^2 x 50 um, "
-                "fog 1-10/1000 um^3, 2449 tracks/mm^2; two pipelines, up to 16 views a batch")
+                "fog 1-10/1000 um^3, 2449 tracks/mm^2")
     # the streaming rate a plain copy gets, beside the 8 TB/s specification
     copy_gbs = measured_copy_gbs(torch)
     out["hbm_copy_measured_GBs"] = round(copy_gbs, 1)
+    out["bin_roofline"]["frac_of_measured"] = round(bin_gbs / copy_gbs, 4)
     for key in ("grain_recognition", "filtering"):
         if key in forms:
             rf = forms[key]["roofline"]
             rf["measured_peak"] = round(copy_gbs, 1)
             rf["frac_of_measured"] = round(rf["achieved"] / copy_gbs, 4)
-    out["without_stage_events"] = {"grains_per_s": round(view.n * args.steps / wall_q, 1),
-                                   "ms_per_step": round(wall_q / args.steps * 1e3, 4)}
-    out["host_input"] = {"grains_per_s": round(view.n / (float(h_lat_ms.mean()) * 1e-3), 1),
-                         "latency_ms": {"p50": round(float(np.percentile(h_lat_ms, 50)), 4),
-                                        "p99": round(float(np.percentile(h_lat_ms, 99)), 4)},
-                         "note": "the c2 view as a host array: PCIe copies of grains and "
-                                 "results inside each call"}
     if forms:
         out["forms"] = forms
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.view_index)
+    if base is not None:
+        out["cpu_baseline"] = base
     print(json.dumps(out))
     return 0
 

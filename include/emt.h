@@ -45,6 +45,8 @@ extern "C" {
 #define EMT_F_STATS 0x1u           /* time every stage with HIP events       */
 #define EMT_F_FP64_FIT_ALWAYS 0x2u /* solve every fit in FP64                */
 #define EMT_F_DEVICE_PTRS 0x4u     /* emt_view_in.xyz point to device memory */
+#define EMT_F_CANDIDATES 0x8u      /* keep every candidate for
+                                      emt_view_candidates                     */
 
 /* Stage indices of emt_call_stats.ms. */
 #define EMT_STAGE_STAGE 0   /* copy grains in                                */
@@ -193,6 +195,19 @@ int emt_create(const emt_config *cfg, emt_ctx **out);
 int emt_track_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views,
                     emt_view_out *out);
 
+/* Candidates of one view of the last successful emt_track_views on a
+ * context created with EMT_F_CANDIDATES: every seed whose grain count
+ * reached the threshold (paper Sec. 2, tracking paragraph; Fig. 4b), before
+ * the exclusive association. *ijn receives n_cand triplets (i, j, n): the
+ * input indices i < j of the seed pair and the number of grains within r of
+ * its line, in the order the device listed them (not the priority order;
+ * sort by (n descending, i, j) for that). Owned by the context, valid until
+ * its next call or emt_destroy. Returns EMT_OK; EMT_EINVAL for a NULL
+ * argument, a view index beyond the last call's views, or a context without
+ * the flag. */
+int emt_view_candidates(emt_ctx *ctx, uint32_t view, const uint32_t **ijn,
+                        uint32_t *n_cand);
+
 /* Statistics of the last successful emt_track_views. After emt_find_grains
  * or emt_filter_stack with EMT_F_STATS, every field is 0 except ms_total:
  * the device time of the recognition or filtering kernels. */
@@ -311,9 +326,24 @@ typedef struct {
     double elapsed_ms; /* since emt_server_create                     */
 } emt_server_stats;
 
-/* Create a server: 1 <= n_pipes <= 8, max_batch_views >= 1. */
+/* Create a server: 1 <= n_pipes <= 8, max_batch_views >= 1; batches have
+ * no grain limit. */
 int emt_server_create(const emt_config *cfg, uint32_t n_pipes,
                       uint32_t max_batch_views, emt_server **out);
+
+/* Limits of a server's batches. max_batch_grains > 0 also closes a batch
+ * before the view that would take it past that many grains (a view larger
+ * than the limit runs alone); 0 is no limit. Smaller batches finish sooner,
+ * so a waiting view is admitted sooner, at some cost in throughput. */
+typedef struct {
+    uint32_t n_pipes;          /* 1..8 pipelines */
+    uint32_t max_batch_views;  /* >= 1 */
+    uint64_t max_batch_grains; /* 0: no limit */
+} emt_server_limits;
+
+/* Create a server with the given limits (as emt_server_create otherwise). */
+int emt_server_create2(const emt_config *cfg, const emt_server_limits *lim,
+                       emt_server **out);
 
 /* Queue one view; its grains are copied before the call returns. *ticket
  * (may be NULL) receives a number that increases with every submission.

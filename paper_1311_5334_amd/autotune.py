@@ -1,20 +1,30 @@
-"""Cell-edge autotuner.
+"""Autotuner of the cell geometry and of the counting kernel's tiles.
 
-For each grain-density bucket of the library's table, time the whole
-tracking path on synthetic views of that density with every candidate cell
-geometry, and write the fastest into ``csrc/cell_table.h`` (rebuild the
-library afterwards). Results never depend on the cells (every grain is
-decided by the exact integer test); only the work does: small cells mean
-more cell runs per seed line, large cells more grains tested per hit.
+Cells (``--cells``, the default): for each grain-density bucket of the
+library's table, time the whole tracking path on synthetic views of that
+density with every candidate cell geometry, and write the fastest into
+``csrc/cell_table.h``. Results never depend on the cells (every grain is
+decided by the exact test); only the work does: small cells mean more cell
+runs per seed line, large cells more grains tested per hit.
 
-    python -m paper_1311_5334_amd.autotune [--table PATH] [--report PATH]
+Tiles (``--tiles``): the counting kernel's queue and launch shapes and the
+cells allowed per grain are compile-time constants. Each candidate value is
+built into a library of its own (``build.build`` with -D overrides, in a
+temporary directory) and timed in a child process on three workloads (one
+c2 view, 8 c5 views and 16 c3 views per call); coordinate descent keeps the
+value that lowers the sum of the workloads' times relative to the starting
+tiles, and the result is written into ``csrc/tile_table.h``.
 
-Needs a GPU. Prints one line per bucket as it goes.
+    python -m paper_1311_5334_amd.autotune [--cells | --tiles] [--report PATH]
+
+Both rewrite a header: rebuild the library afterwards. Needs a GPU. Prints a
+line per timed candidate as it goes.
 """
 from __future__ import annotations
 
 import argparse
 import itertools
+import json
 import os
 import sys
 import time
@@ -76,12 +86,187 @@ constexpr int kTunedCells[8][3] = {{
     open(path, "w").write(text)
 
 
+TILE_TABLE = os.path.join(HERE, "csrc", "tile_table.h")
+# candidate values of each tile constant (see csrc/tile_table.h)
+TILE_SPACE = {
+    "EMT_COUNT_PIECE": (2, 3, 4, 6),
+    "EMT_COUNT_LANE_PIECES": (4, 8, 12),
+    "EMT_COUNT_FETCH": (2, 3, 4, 6),
+    "EMT_CHUNK_SEEDS": (64, 128, 256),
+    "EMT_COUNT_BLOCKS": (1024, 2048),
+    "EMT_CELLS_PER_GRAIN": (4, 8, 16),
+}
+TILE_COMMENTS = {
+    "EMT_COUNT_PIECE": "grains a flush lane tests per queue entry",
+    "EMT_COUNT_LANE_PIECES": "queue entries a lane adds per step",
+    "EMT_COUNT_FETCH": "cell pencils a lane fetches per step",
+    "EMT_CHUNK_SEEDS": "seeds a wave takes at a time (single views)",
+    "EMT_COUNT_BLOCKS": "workgroups of the counting kernel",
+    "EMT_CELLS_PER_GRAIN": "cells a view may use per grain (plus 4096)",
+}
+WORKLOADS = ("c2", "c5x8", "c3x16")
+
+
+def read_tiles(path: str = TILE_TABLE) -> dict:
+    """The values tile_table.h sets now."""
+    import re
+    text = open(path).read()
+    return {k: int(re.search(rf"#define {k} (\d+)", text).group(1)) for k in TILE_SPACE}
+
+
+def write_tiles(path: str, tiles: dict, summary: str) -> None:
+    lines = []
+    for k in TILE_SPACE:
+        lines.append(f"#ifndef {k}\n#define {k} {tiles[k]}  // {TILE_COMMENTS[k]}\n#endif")
+    body = "\n".join(lines)
+    text = f"""// tile_table.h -- queue sizes and launch shapes of the counting kernel and
+// the cell budget per grain, chosen by paper_1311_5334_amd/autotune.py
+// --tiles from timings of the whole path; -D on the compiler line overrides
+// each value.
+{summary}
+#ifndef EMT_TILE_TABLE_H
+#define EMT_TILE_TABLE_H
+
+{body}
+
+// queue capacities that follow from the above
+#ifndef EMT_COUNT_PIECE_CAP
+#define EMT_COUNT_PIECE_CAP (128 * EMT_COUNT_LANE_PIECES)
+#endif
+#ifndef EMT_COUNT_RUN_CAP
+#define EMT_COUNT_RUN_CAP (64 * EMT_COUNT_FETCH)
+#endif
+
+#endif
+"""
+    open(path, "w").write(text)
+
+
+def _workload_views(path: str) -> None:
+    """The tile workloads' views, generated once and saved for the children."""
+    from paper_1311_5334_amd import synth
+    arrs = {"c2_0": synth.make_c2(0).xyz}
+    for i in range(8):
+        arrs[f"c5_{i}"] = synth.make_c5(i).xyz
+    for i in range(16):
+        arrs[f"c3_{i}"] = synth.make_c3(i).xyz
+    np.savez(path, **arrs)
+
+
+def time_library(lib: str, views_path: str, calls: int = 3) -> dict:
+    """Child-process mode: load one library build and time the workloads
+    (median device time of the whole path per call, ms)."""
+    import torch
+    from paper_1311_5334_amd import emt
+    emt.load(lib)
+    z = np.load(views_path)
+    groups = {"c2": [z["c2_0"]], "c5x8": [z[f"c5_{i}"] for i in range(8)],
+              "c3x16": [z[f"c3_{i}"] for i in range(16)]}
+    out = {}
+    for name in WORKLOADS:
+        devs = [torch.from_numpy(x).to("cuda:0").contiguous() for x in groups[name]]
+        torch.cuda.synchronize()
+        with emt.Tracker(device=0, flags=emt.EMT_F_DEVICE_PTRS | emt.EMT_F_STATS) as tr:
+            tr(devs)
+            tr(devs)
+            ms = []
+            for _ in range(calls):
+                tr(devs)
+                ms.append(tr.stats()["ms_total"])
+        out[name] = float(np.median(ms))
+    return out
+
+
+def tune_tiles(report: str | None, passes: int = 2) -> int:
+    import subprocess
+    import tempfile
+    from paper_1311_5334_amd import build
+    tmp = tempfile.mkdtemp(prefix="emt_tiles_")
+    views_path = os.path.join(tmp, "views.npz")
+    _workload_views(views_path)
+    cache = {}
+    t_start = time.time()
+
+    def timed(tiles: dict) -> dict:
+        key = tuple(sorted(tiles.items()))
+        if key in cache:
+            return cache[key]
+        tag = "_".join(str(v) for _, v in key)
+        lib = os.path.join(tmp, f"libemt_{tag}.so")
+        build.build(lib=lib, defines=tiles, objdir=os.path.join(tmp, "obj_" + tag))
+        r = subprocess.run([sys.executable, "-m", "paper_1311_5334_amd.autotune",
+                            "--time-lib", lib, views_path], capture_output=True, text=True,
+                           timeout=600)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout[-2000:] + r.stderr[-2000:])
+            raise RuntimeError(f"timing of {tag} failed")
+        res = json.loads(r.stdout.strip().splitlines()[-1])
+        cache[key] = res
+        print(f"  {dict(key)}: " + ", ".join(f"{k} {v:.3f} ms" for k, v in res.items()) +
+              f" [{time.time() - t_start:.0f} s]", flush=True)
+        return res
+
+    start = read_tiles()
+    base = timed(start)
+
+    def score(res: dict) -> float:
+        return sum(res[w] / base[w] for w in WORKLOADS) / len(WORKLOADS)
+
+    cur = dict(start)
+    for _ in range(passes):
+        changed = False
+        for k, values in TILE_SPACE.items():
+            best_v, best_s = cur[k], score(timed(cur))
+            for v in values:
+                trial = dict(cur, **{k: v})
+                sc = score(timed(trial))
+                if sc < best_s - 0.005:
+                    best_v, best_s = v, sc
+            if best_v != cur[k]:
+                cur[k] = best_v
+                changed = True
+        if not changed:
+            break
+    final = timed(cur)
+    lines = [f"starting tiles {start}: " + ", ".join(f"{w} {base[w]:.3f} ms" for w in WORKLOADS),
+             f"chosen tiles {cur}: " + ", ".join(f"{w} {final[w]:.3f} ms" for w in WORKLOADS) +
+             f" (mean time ratio {score(final):.3f})",
+             f"{len(cache)} builds timed"]
+    write_tiles(TILE_TABLE, cur, "\n".join("//   " + ln for ln in lines))
+    print("wrote", TILE_TABLE, flush=True)
+    if report:
+        with open(report, "w") as f:
+            f.write("# Tile autotune\n\nCommand: `python -m paper_1311_5334_amd.autotune "
+                    f"--tiles --report {report}`\n\nSpace: {TILE_SPACE}. Workloads: c2 view 0 "
+                    "alone, c5 views 0-7 in one call, c3 views 0-15 in one call (device-resident); "
+                    "time: median device time of the whole path per call, 3 calls after 2 "
+                    "warm-up calls, each candidate built as a library of its own. Coordinate "
+                    "descent on the mean of the three times relative to the starting tiles.\n\n")
+            for ln in lines:
+                f.write(f"- {ln}\n")
+            f.write("\n| tiles | " + " | ".join(WORKLOADS) + " |\n|---|" +
+                    "---:|" * len(WORKLOADS) + "\n")
+            for key, res in cache.items():
+                f.write(f"| {dict(key)} | " + " | ".join(f"{res[w]:.3f}" for w in WORKLOADS) +
+                        " |\n")
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
+    mode = ap.add_mutually_exclusive_group()
+    mode.add_argument("--cells", action="store_true", help="tune the cell table (default)")
+    mode.add_argument("--tiles", action="store_true", help="tune the counting kernel's tiles")
+    mode.add_argument("--time-lib", nargs=2, metavar=("LIB", "VIEWS"), help=argparse.SUPPRESS)
     ap.add_argument("--table", default=TABLE)
     ap.add_argument("--report", default=None, help="also write a markdown summary here")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))
+    if args.time_lib:
+        print(json.dumps(time_library(*args.time_lib)), flush=True)
+        return 0
+    if args.tiles:
+        return tune_tiles(args.report)
     import torch
     from paper_1311_5334_amd import emt, synth
 

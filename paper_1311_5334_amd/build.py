@@ -22,9 +22,10 @@ FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
          "-Wall", "-Wshadow", "-I" + INCLUDE, "-I" + CSRC]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJDIR, src + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, objdir: str, defines: tuple) -> str:
+    obj = os.path.join(objdir, src + ".o")
+    cmd = [HIPCC, *FLAGS, *[f"-D{k}={v}" for k, v in defines], "-c",
+           os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
@@ -32,21 +33,26 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source for gfx950 and link libemt.so (always rebuilds)."""
-    os.makedirs(OBJDIR, exist_ok=True)
+def build(verbose: bool = False, lib: str = LIB, defines: dict | None = None,
+          objdir: str = OBJDIR) -> str:
+    """Compile every source for gfx950 and link the library (always
+    rebuilds). defines: tuning macros (-D) overriding the values the sources
+    take from csrc/tile_table.h; the autotuner builds such variants into
+    directories of their own."""
+    os.makedirs(objdir, exist_ok=True)
+    dfs = tuple(sorted((defines or {}).items()))
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, objdir, dfs), SOURCES))
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("link of libemt.so failed")
-    os.replace(tmp, LIB)
+        raise RuntimeError(f"link of {lib} failed")
+    os.replace(tmp, lib)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib)
+    return lib
 
 
 if __name__ == "__main__":

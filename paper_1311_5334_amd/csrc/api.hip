@@ -25,7 +25,8 @@ using namespace emt;
 
 namespace {
 
-constexpr uint32_t kKnownFlags = EMT_F_STATS | EMT_F_FP64_FIT_ALWAYS | EMT_F_DEVICE_PTRS;
+constexpr uint32_t kKnownFlags =
+    EMT_F_STATS | EMT_F_FP64_FIT_ALWAYS | EMT_F_DEVICE_PTRS | EMT_F_CANDIDATES;
 // Cell edges (units) for an axis left at 0 when the others are given:
 // short along x, where a cell row is one contiguous run, and about the
 // paper's 7.5 um hash cell across it.
@@ -38,6 +39,8 @@ struct DevArena {
 };
 
 }  // namespace
+
+
 
 struct emt_ctx {
     emt_config cfg{};
@@ -72,7 +75,11 @@ struct emt_ctx {
     // results, in mapped pinned memory written by the device
     HostOut h{};                  // host addresses
     size_t cap_out_views = 0, cap_out_cnt = 0, cap_out_tracks = 0, cap_out_grains = 0;
-    size_t cap_vs = 0, cap_vc = 0, cap_vn = 0, cap_vo = 0, cap_ve = 0;
+    size_t cap_vs = 0, cap_vc = 0, cap_vn = 0, cap_vo = 0, cap_ve = 0, cap_cands = 0;
+    // candidates kept (EMT_F_CANDIDATES): first candidate of each view of
+    // the last call, and the number of views it had
+    std::vector<uint32_t> cand_off;
+    uint32_t last_views = 0;
 
     emt_call_stats last{};
 
@@ -237,7 +244,8 @@ int mapped(emt_ctx *ctx, T *&host, T *&dev, size_t &cap, size_t n) {
 // layout).
 size_t grain_bytes(size_t n) {
     return bytes_of<int32_t>(3 * n) + 4 * bytes_of<uint32_t>(n) + bytes_of<uint32_t>(n + 1) +
-           bytes_of<int4>(n) + bytes_of<uint8_t>(n) + bytes_of<unsigned long long>(n);
+           2 * bytes_of<int4>(n + kSortedSpare) + bytes_of<uint8_t>(n) +
+           bytes_of<unsigned long long>(n);
 }
 size_t seed_bytes(size_t n) {
     return bytes_of<uint2>(n) + bytes_of<uint32_t>(n) + bytes_of<uint32_t>(n + 1);
@@ -279,7 +287,8 @@ int ensure(emt_ctx *ctx, Caps &c) {
         d.rank = carve<uint32_t>(p, n);
         d.seed_cnt = carve<uint32_t>(p, n);
         d.seed_off = carve<uint32_t>(p, n + 1);
-        d.sg = carve<int4>(p, n);
+        d.sg = carve<int4>(p, n + kSortedSpare);
+        d.sgf = carve<float4>(p, n + kSortedSpare);
         d.used = carve<uint8_t>(p, n);
         d.owner = carve<unsigned long long>(p, n);
         ctx->cap_n = (uint32_t)n;
@@ -383,6 +392,10 @@ int ensure(emt_ctx *ctx, Caps &c) {
         if ((rc = mapped(ctx, h.view_err, o.view_err, ctx->cap_ve, nv))) return rc;
         if ((rc = mapped(ctx, h.tracks, o.tracks, ctx->cap_out_tracks, c.cand_cap))) return rc;
         if ((rc = mapped(ctx, h.grains, o.grains, ctx->cap_out_grains, c.mem_cap))) return rc;
+        if (ctx->cfg.flags & EMT_F_CANDIDATES) {
+            if ((rc = mapped(ctx, h.cands, o.cands, ctx->cap_cands, 3 * (size_t)c.cand_cap)))
+                return rc;
+        }
     }
     return EMT_OK;
 }
@@ -558,7 +571,7 @@ void fill_grids(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views) {
         G.grain_off = go;
         G.n = views[v].n_grains;
         G.cell_off = co;
-        G.cell_cap = 4u * views[v].n_grains + 4096u;
+        G.cell_cap = kCellsPerGrain * views[v].n_grains + kCellsBase;
         go += G.n;
         co += G.cell_cap + 1;
     }
@@ -578,7 +591,8 @@ int batch_caps(const emt_ctx *ctx, unsigned long long n_total, uint32_t n_views,
     Caps c{};
     c.n_total = bucket(n_total, 1024);
     c.n_views = bucket(n_views, 1);
-    const unsigned long long cells_cap = 4ull * c.n_total + 4097ull * c.n_views;
+    const unsigned long long cells_cap =
+        (unsigned long long)kCellsPerGrain * c.n_total + (kCellsBase + 1ull) * c.n_views;
     if (cells_cap >= (1ull << 31)) return EMT_ERANGE;
     c.n_cells = (uint32_t)cells_cap;
     c.max_view_n = std::min(c.n_total, bucket(max_n, 64));
@@ -743,7 +757,7 @@ int begin_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views) {
     uint32_t max_n = 0;
     for (uint32_t v = 0; v < n_views; ++v) {
         n_total += views[v].n_grains;
-        n_cells += 4ull * views[v].n_grains + 4096 + 1;
+        n_cells += (unsigned long long)kCellsPerGrain * views[v].n_grains + kCellsBase + 1;
         max_n = std::max(max_n, views[v].n_grains);
     }
     Caps c{};
@@ -842,6 +856,20 @@ int finish_views(emt_ctx *ctx, emt_view_out *out) {
         o.stats.n_seeds = ctx->h.view_seeds[v];
         o.stats.n_candidates = ctx->h.view_cand[v];
         o.stats.n_tracks = nt;
+    }
+    if (ctx->cfg.flags & EMT_F_CANDIDATES) {
+        try {
+            ctx->cand_off.resize((size_t)n_views + 1);
+        } catch (...) {
+            return EMT_ENOMEM;
+        }
+        uint32_t o = 0;
+        for (uint32_t v = 0; v < n_views; ++v) {
+            ctx->cand_off[v] = o;
+            o += ctx->h.view_cand[v];
+        }
+        ctx->cand_off[n_views] = o;
+        ctx->last_views = n_views;
     }
     ctx->next_wide = std::max(6, std::min(max_wide_rounds(), (int)h.rounds + 2));
     emt_call_stats &st = ctx->last;
@@ -1031,6 +1059,17 @@ int emt_find_grains(emt_ctx *ctx, const uint8_t *stack, const emt_stack_geom *ge
     return rc;
 }
 
+int emt_view_candidates(emt_ctx *ctx, uint32_t view, const uint32_t **ijn, uint32_t *n_cand) {
+    if (!ctx || !ijn || !n_cand) return EMT_EINVAL;
+    *ijn = nullptr;
+    *n_cand = 0;
+    if (!(ctx->cfg.flags & EMT_F_CANDIDATES) || view >= ctx->last_views) return EMT_EINVAL;
+    const uint32_t a = ctx->cand_off[view], b = ctx->cand_off[view + 1];
+    *ijn = ctx->h.cands + 3 * (size_t)a;
+    *n_cand = b - a;
+    return EMT_OK;
+}
+
 int emt_last_stats(emt_ctx *ctx, emt_call_stats *stats) {
     if (!ctx || !stats) return EMT_EINVAL;
     *stats = ctx->last;
@@ -1048,7 +1087,7 @@ void emt_destroy(emt_ctx *ctx) {
         if (a->p) (void)hipFree(a->p);
     void *hosts[] = {ctx->h_small, ctx->h_xyz, ctx->h_grids, ctx->h_desc, ctx->h.cnt, ctx->h.view_seeds,
                      ctx->h.view_cand, ctx->h.view_ntr, ctx->h.view_tr_off, ctx->h.view_err,
-                     ctx->h.tracks, ctx->h.grains};
+                     ctx->h.tracks, ctx->h.grains, ctx->h.cands};
     for (void *p : hosts)
         if (p) (void)hipHostFree(p);
     for (int i = 0; i <= EMT_N_STAGES; ++i)

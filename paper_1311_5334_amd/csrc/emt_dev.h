@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include "emt.h"
+#include "tile_table.h"
 
 namespace emt {
 
@@ -15,6 +16,13 @@ constexpr int kSpanMax = 1 << 18;  // per-axis coordinate span limit (units)
 constexpr uint32_t kNMax = 1u << 20;
 constexpr int kRMax = 4096;
 constexpr int kBlock = 256;
+// Cells a view may use: kCellsPerGrain per grain plus kCellsBase; cell edges
+// are doubled until the grid fits.
+constexpr uint32_t kCellsPerGrain = EMT_CELLS_PER_GRAIN;
+constexpr uint32_t kCellsBase = 4096;
+// Entries of the sorted-grain array past the last grain: kernels that load
+// a fixed group of consecutive grains may read (and then ignore) them.
+constexpr uint32_t kSortedSpare = 8;
 
 // Per view. Host fills grain_off, n, cell_off, cell_cap and resets lo/hi;
 // the device fills the rest (bounding box, then cell geometry).
@@ -110,6 +118,7 @@ struct HostOut {
     int32_t *view_err;
     emt_track *tracks;     // cand_cap
     uint32_t *grains;      // mem_cap
+    uint32_t *cands;       // 3 cand_cap (i, j, n), or null when not kept
 };
 
 // All device buffers of one call, as raw pointers.
@@ -121,7 +130,8 @@ struct DevPtrs {
     uint32_t *rank;       // N
     uint32_t *cell_count; // C
     uint32_t *cell_start; // C
-    int4 *sg;             // N sorted grains: x, y, z relative to lo; w = input index
+    int4 *sg;             // N (+ kSortedSpare) sorted grains: x, y, z relative to lo; w = input index
+    float4 *sgf;          // N (+ kSortedSpare): x, y, z of sg as floats (exact), w = 0
     uint32_t *seed_cnt;   // N: seeds per anchor
     uint32_t *seed_off;   // N + 1
     uint2 *seeds;         // seed_cap
@@ -192,6 +202,12 @@ struct GrainBufs {
     int32_t *out;         // 3 * max_out: x, y, z per grain, 0.01 um units
     uint32_t max_out;
 };
+
+// Tiles of the grain recognition: pixels a tile streams, staging slots (two
+// bytes each) per tile, tiles summed per group.
+constexpr uint32_t kGrainTilePix = 8192;
+constexpr uint32_t kGrainTileGrains = kGrainTilePix / 2;
+constexpr uint32_t kGrainTileGroup = 64;
 
 size_t grain_tile_count(const StackGeom &G);
 size_t grain_group_count(const StackGeom &G);

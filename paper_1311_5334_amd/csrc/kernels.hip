@@ -19,21 +19,10 @@ namespace emt {
 
 namespace {
 
-// Tuning constants; -D on the compiler line overrides them.
+// Tuning constants; -D on the compiler line overrides them (the counting
+// kernel's tiles come from tile_table.h, through emt_dev.h).
 #ifndef EMT_DYN_MIN_SEEDS
 #define EMT_DYN_MIN_SEEDS 8000000
-#endif
-#ifndef EMT_COUNT_SLOT_CAP
-#define EMT_COUNT_SLOT_CAP 4096
-#endif
-#ifndef EMT_COUNT_RUN_CAP
-#define EMT_COUNT_RUN_CAP 512
-#endif
-#ifndef EMT_COUNT_LANE_CAP
-#define EMT_COUNT_LANE_CAP 64
-#endif
-#ifndef EMT_COUNT_FETCH
-#define EMT_COUNT_FETCH 8
 #endif
 #ifndef EMT_MEMBER_LANES
 #define EMT_MEMBER_LANES 4
@@ -43,9 +32,6 @@ namespace {
 #endif
 #ifndef EMT_MEMBER_SLOT_CAP
 #define EMT_MEMBER_SLOT_CAP 4096
-#endif
-#ifndef EMT_CHUNK_SEEDS
-#define EMT_CHUNK_SEEDS 128
 #endif
 constexpr float kMargin = 4.0f;  // units added to every cell window
 constexpr int kScanItems = 8;
@@ -331,15 +317,16 @@ __global__ void __launch_bounds__(kBlock) k_hist(const int32_t *xyz, const ViewG
 __global__ void __launch_bounds__(kBlock) k_scatter(const int32_t *xyz, const ViewGrid *grids,
                                                     const uint32_t *cell_of, const uint32_t *rank,
                                                     const uint32_t *cell_start, int4 *sg,
-                                                    const BatchDesc *desc) {
+                                                    float4 *sgf, const BatchDesc *desc) {
     const uint32_t v = blockIdx.y;
     if (v >= desc->n_views) return;
     const ViewGrid G = grids[v];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < G.n; i += gridDim.x * blockDim.x) {
         const size_t g = (size_t)G.grain_off + i;
         const uint32_t pos = cell_start[cell_of[g]] + rank[g];
-        sg[pos] = make_int4(xyz[3 * g] - G.lo[0], xyz[3 * g + 1] - G.lo[1], xyz[3 * g + 2] - G.lo[2],
-                            (int)i);
+        const int x = xyz[3 * g] - G.lo[0], y = xyz[3 * g + 1] - G.lo[1], z = xyz[3 * g + 2] - G.lo[2];
+        sg[pos] = make_int4(x, y, z, (int)i);
+        sgf[pos] = make_float4((float)x, (float)y, (float)z, 0.0f);
     }
 }
 
@@ -988,31 +975,69 @@ __global__ void __launch_bounds__(kBlock) k_members(DevPtrs d, Caps c, Params P)
 // time is the sum of its lines' work rather than a multiple of the longest
 // one. Hit counts of a closed slot are final after the next queue flush,
 // which writes them out and frees the slot.
+//
+// The queue holds pieces: each run a lane queues is cut into pieces of at
+// most kPiece consecutive grains, and the flush gives every lane one piece.
+// The lane maps its piece to the run by one popcount, reads the seed's line
+// constants once, issues the loads of all kPiece grains together and tests
+// them against the one line, so the mapping and the line constants are paid
+// once per piece and the grain loads of a piece are in flight together.
 constexpr int kCountSlots = 128;
-constexpr int kCountSlotCap = EMT_COUNT_SLOT_CAP;  // queued tests per wave
-constexpr int kCountRunCap = EMT_COUNT_RUN_CAP;    // queued runs per wave
-constexpr int kCountLaneCap = EMT_COUNT_LANE_CAP;  // tests a lane queues per step
-constexpr int kCountMaskWords = kCountSlotCap / 64;
+constexpr int kPiece = EMT_COUNT_PIECE;             // grains per queued piece
+constexpr int kPieceCap = EMT_COUNT_PIECE_CAP;      // queued pieces per wave
+constexpr int kLanePieces = EMT_COUNT_LANE_PIECES;  // pieces a lane queues per step
+constexpr int kCountRunCap = EMT_COUNT_RUN_CAP;     // queued runs per wave
+constexpr int kPieceWords = kPieceCap / 64;
 constexpr int kChunkSeeds = EMT_CHUNK_SEEDS;
 constexpr int kFetch = EMT_COUNT_FETCH;  // pencils a lane fetches per step
 static_assert(64 * kFetch <= kCountRunCap, "a step's runs must fit the run queue");
-static_assert(kCountSlotCap >= 64 * kCountLaneCap, "a step's tests must fit the slot queue");
-static_assert(kCountMaskWords <= 64, "one mask word per lane");
+static_assert(64 * kLanePieces <= kPieceCap, "a step's pieces must fit the queue");
+static_assert(kPieceWords <= 64 && kPieceCap % 64 == 0, "one mask word per lane");
+static_assert(kPieceCap <= 4096 && kPiece * kLanePieces < 8192, "run record fields");
+static_assert(kPiece >= 1 && (uint32_t)kPiece - 1u <= kSortedSpare, "piece size");
 
 template <bool kFinite>
 struct CountLds {
-    int4 pa[kCountSlots];
-    int4 pb[kCountSlots];
+    // line constants per seed slot (floats): d, -d, -(g_i x d), the band
+    // [tlo, thi] of the FP32 test, and the sorted position of g_i
+    float4 la[kCountSlots];  // dx, dy, dz, tlo
+    float4 lb[kCountSlots];  // -dx, -dy, -dz, thi
+    float4 lc[kCountSlots];  // -ex, -ey, -ez, (bits) sorted position of g_i
     int2 pc[kFinite ? kCountSlots : 1];  // finite cylinder: bounds of g_k.d
     uint32_t cnt[kCountSlots];
-    unsigned long long mask[kCountMaskWords];
-    uint32_t before[kCountMaskWords];
-    uint2 run[kCountRunCap];  // first grain, first queue slot | seed slot << 16
+    unsigned long long mask[kPieceWords];  // bit s: a run starts at piece s
+    uint32_t before[kPieceWords];          // runs starting before word w
+    uint2 run[kCountRunCap];  // first grain; first piece | seed slot << 12 | grains << 19
 };
 
+// The counting test in FP32, decided exactly. With coordinates in [0, 2^18]
+// (exact floats) and |d| < 2^12, c = g_k x d - g_i x d is formed by two
+// fused multiply-adds a component from d, -d and the rounded -(g_i x d).
+// Each rounding is at most 2^-24 of a magnitude below 2^18 (1 + sqrt 2)|d|,
+// so each component is within 0.06 |d| of the exact one and |c| within
+// 0.104 |d|. A grain is certainly inside when the FP32 |c|^2 is at most
+// tlo = (r - 1/8)^2 |d|^2 and certainly outside above thi = (r + 1/8)^2
+// |d|^2, both widened by 2^-20 for the rounding of the squares (tlo < 0
+// when r <= 1/8); in between the test is redone in int64.
+__device__ __forceinline__ void line_consts(int4 gi, int dx, int dy, int dz, int r, uint32_t p,
+                                            float4 &A, float4 &B, float4 &C) {
+    const long long D = (long long)dx * dx + (long long)dy * dy + (long long)dz * dz;
+    const double sd = sqrt((double)D);
+    const double lo = (double)r * sd - 0.125 * sd, hi = (double)r * sd + 0.125 * sd;
+    const float tlo = lo > 0.0 ? (float)(lo * lo * (1.0 - 0x1p-20)) : -1.0f;
+    const float thi = (float)(hi * hi * (1.0 + 0x1p-20));
+    const long long ex = (long long)gi.y * dz - (long long)gi.z * dy;
+    const long long ey = (long long)gi.z * dx - (long long)gi.x * dz;
+    const long long ez = (long long)gi.x * dy - (long long)gi.y * dx;
+    A = make_float4((float)dx, (float)dy, (float)dz, tlo);
+    B = make_float4((float)-dx, (float)-dy, (float)-dz, thi);
+    C = make_float4((float)-ex, (float)-ey, (float)-ez, __uint_as_float(p));
+}
+
 template <bool kFinite>
-__device__ __forceinline__ void count_flush(CountLds<kFinite> &Q, uint32_t qn, int tol_r, const int4 *__restrict__ sg,
-                                            int lane) {
+__device__ __forceinline__ void count_flush(CountLds<kFinite> &Q, uint32_t qn, int tol_r,
+                                            const int4 *__restrict__ sg,
+                                            const float4 *__restrict__ sgf, int lane) {
     wave_lds_sync();
     const uint32_t nw = (qn + 63) >> 6;
     {
@@ -1028,13 +1053,52 @@ __device__ __forceinline__ void count_flush(CountLds<kFinite> &Q, uint32_t qn, i
         if (s < qn) {
             const uint32_t r = Q.before[w] + (uint32_t)__popcll(word & upto) - 1u;
             const uint2 rec = Q.run[r];
-            const uint32_t tag = rec.y;
-            const uint32_t kk = rec.x + (s - (tag & 0xffffu));
-            const uint32_t sl = tag >> 16;
-            const int4 h = sg[kk];
-            if (cyl_hit(h, Q.pa[sl], Q.pb[sl], tol_r) &&
-                (!kFinite || axial_ok(h, Q.pa[sl], Q.pc[sl])))
-                atomicAdd(&Q.cnt[sl], 1u);
+            const uint32_t q = s - (rec.y & 0xfffu);  // piece of the run
+            const uint32_t sl = (rec.y >> 12) & 0x7fu;
+            const uint32_t k0 = rec.x + (uint32_t)kPiece * q;
+            const uint32_t m = min((rec.y >> 19) - (uint32_t)kPiece * q, (uint32_t)kPiece);
+            const float4 A = Q.la[sl], B = Q.lb[sl], C = Q.lc[sl];
+            // the sorted grains carry kPiece - 1 spare entries past the
+            // last one, so a piece's loads stay in bounds
+            const float4 *pp = sgf + k0;
+            float4 h[kPiece];
+#pragma unroll
+            for (int t = 0; t < kPiece; ++t) h[t] = pp[t];
+            uint32_t n = 0, amb = 0;
+#pragma unroll
+            for (int t = 0; t < kPiece; ++t) {
+                const float c0 = fmaf(h[t].y, A.z, fmaf(h[t].z, B.y, C.x));
+                const float c1 = fmaf(h[t].z, A.x, fmaf(h[t].x, B.z, C.y));
+                const float c2 = fmaf(h[t].x, A.y, fmaf(h[t].y, B.x, C.z));
+                const float fc = fmaf(c0, c0, fmaf(c1, c1, c2 * c2));
+                bool ok = (uint32_t)t < m;
+                if constexpr (kFinite) {
+                    const int4 hi = make_int4((int)h[t].x, (int)h[t].y, (int)h[t].z, 0);
+                    const int4 Ai = make_int4((int)A.x, (int)A.y, (int)A.z, 0);
+                    ok = ok && axial_ok(hi, Ai, Q.pc[sl]);
+                }
+                const bool in_lo = fc <= A.w, in_hi = fc <= B.w;
+                n += (ok && in_lo) ? 1u : 0u;
+                amb |= (ok && in_hi && !in_lo) ? (1u << t) : 0u;
+            }
+            if (amb) {
+                // inside the band: decide in int64 from the integer grains (rare)
+                const int dx = (int)A.x, dy = (int)A.y, dz = (int)A.z;
+                const long long D = (long long)dx * dx + (long long)dy * dy + (long long)dz * dz;
+                const long long thr = (long long)tol_r * tol_r * D;
+                const int4 gi = sg[__float_as_uint(C.w)];
+#pragma unroll
+                for (int t = 0; t < kPiece; ++t) {
+                    if (amb & (1u << t)) {
+                        const int4 g = sg[k0 + (uint32_t)t];
+                        const long long wx = g.x - gi.x, wy = g.y - gi.y, wz = g.z - gi.z;
+                        const long long e0 = wy * dz - wz * dy, e1 = wz * dx - wx * dz,
+                                        e2 = wx * dy - wy * dx;
+                        n += e0 * e0 + e1 * e1 + e2 * e2 <= thr ? 1u : 0u;
+                    }
+                }
+            }
+            if (n) atomicAdd(&Q.cnt[sl], n);
         }
     }
     wave_lds_sync();
@@ -1048,7 +1112,7 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
     const int lane = lane_id();
     CountLds<kFinite> &Q = sQ[threadIdx.x >> 6];
     const uint32_t n_items = d.cnt->n_seeds_ok;
-    if (lane < kCountMaskWords) Q.mask[lane] = 0ull;
+    if (lane < kPieceWords) Q.mask[lane] = 0ull;
     wave_lds_sync();
     unsigned long long tests = 0, hits = 0;
     // Which seeds a wave counts. Few seeds (one view or so, whose grains fit
@@ -1130,10 +1194,11 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
                     th1 = th;
                 }
                 if constexpr (kFinite) Q.pc[cur] = axial_bounds(gi, dx, dy, dz, P.cyl_ext);
-                LineTest L;
-                L.init(gi, dx, dy, dz, P.r);
-                Q.pa[cur] = make_int4(dx, dy, dz, __float_as_int(L.tlo));
-                Q.pb[cur] = make_int4((int)L.ex, (int)L.ey, (int)L.ez, __float_as_int(L.thi));
+                float4 A, B, C;
+                line_consts(gi, dx, dy, dz, P.r, pq.x, A, B, C);
+                Q.la[cur] = A;
+                Q.lb[cur] = B;
+                Q.lc[cur] = C;
                 Q.cnt[cur] = 0;
                 W.init(&d.grids[v], gi, dx, dy, dz, P.r, true, 0, 1, kFinite ? P.cyl_ext : -1);
                 have = true;
@@ -1147,23 +1212,26 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
 #pragma unroll
                 for (int f = 0; f < kFetch; ++f) W.fetch(d.cell_start, run[f]);
             }
-            // queue up to kCountLaneCap grains of the lane's runs
-            uint32_t budget = kCountLaneCap, mine = 0, nrun = 0;
-            uint32_t len[kFetch];
+            // queue up to kLanePieces pieces of the lane's runs
+            uint32_t left = kLanePieces, mine = 0, nrun = 0, mtests = 0;
+            uint32_t len[kFetch], np[kFetch];
 #pragma unroll
             for (int f = 0; f < kFetch; ++f) {
-                len[f] = min(run[f].e > run[f].k ? run[f].e - run[f].k : 0u, budget);
-                budget -= len[f];
-                mine += len[f];
+                const uint32_t avail = run[f].e > run[f].k ? run[f].e - run[f].k : 0u;
+                len[f] = min(avail, (uint32_t)kPiece * left);
+                np[f] = (len[f] + (uint32_t)kPiece - 1u) / (uint32_t)kPiece;
+                left -= np[f];
+                mine += np[f];
+                mtests += len[f];
                 nrun += len[f] ? 1u : 0u;
             }
             const uint32_t pk = mine | (nrun << 16);
             const uint32_t incl = wave_incl_scan_dpp(pk);
             const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
             // room first: test what is queued if this step's runs do not fit
-            if (qn + (tot & 0xffffu) > (uint32_t)kCountSlotCap ||
+            if (qn + (tot & 0xffffu) > (uint32_t)kPieceCap ||
                 nr + (tot >> 16) > (uint32_t)kCountRunCap) {
-                count_flush(Q, qn, P.r, d.sg, lane);
+                count_flush(Q, qn, P.r, d.sg, d.sgf, lane);
                 qn = 0;
                 nr = 0;
                 finalize();
@@ -1172,20 +1240,20 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
                 const uint32_t ex = incl - pk;
                 uint32_t pos = qn + (ex & 0xffffu);
                 uint32_t ri = nr + (ex >> 16);
-                const uint32_t tag = (uint32_t)cur << 16;
+                const uint32_t tag = (uint32_t)cur << 12;
 #pragma unroll
                 for (int f = 0; f < kFetch; ++f) {
                     if (len[f]) {
-                        Q.run[ri++] = make_uint2(run[f].k, pos | tag);
+                        Q.run[ri++] = make_uint2(run[f].k, pos | tag | (len[f] << 19));
                         atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
-                        pos += len[f];
+                        pos += np[f];
                         run[f].k += len[f];
                     }
                 }
             }
             qn += tot & 0xffffu;
             nr += tot >> 16;
-            tests += mine;
+            tests += mtests;
             // a seed whose walk ended and whose runs are all queued is closed
             bool queued = true;
 #pragma unroll
@@ -1198,7 +1266,7 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
             const uint32_t n_blocked = (uint32_t)__popcll(__ballot(blocked));
             const bool all_done = __ballot(have) == 0 && next >= end && !more;
             if (all_done || n_blocked > 16) {
-                if (qn) count_flush(Q, qn, P.r, d.sg, lane);
+                if (qn) count_flush(Q, qn, P.r, d.sg, d.sgf, lane);
                 qn = 0;
                 nr = 0;
                 finalize();
@@ -1826,6 +1894,16 @@ __global__ void __launch_bounds__(kBlock) k_copy_out(DevPtrs d, Caps c) {
     for (uint32_t i = tid; i < words; i += nt) dst[i] = src[i];
     const uint32_t ng = cn.n_track_grains <= c.mem_cap ? cn.n_track_grains : 0u;
     for (uint32_t i = tid; i < ng; i += nt) d.out.grains[i] = d.out_grains[i];
+    if (d.out.cands) {
+        // candidates as input-index pairs with their counts, in list order
+        const uint32_t nc = cn.n_cand <= c.cand_cap ? cn.n_cand : 0u;
+        for (uint32_t i = tid; i < nc; i += nt) {
+            const Cand cd = d.cand[i];
+            d.out.cands[3 * i] = (uint32_t)d.sg[cd.p].w;
+            d.out.cands[3 * i + 1] = (uint32_t)d.sg[cd.q].w;
+            d.out.cands[3 * i + 2] = cd.n;
+        }
+    }
 }
 
 // ---------------------------------------------------- grain recognition
@@ -1873,6 +1951,9 @@ constexpr uint32_t kTileGrains = kTilePix / 2;              // staging slots per
 constexpr uint32_t kTileGroup = 64;                         // tiles per atomic sum
 constexpr uint32_t kCandCap = 2048;                         // candidates listed per round
 static_assert(kTilePix <= 65536u, "tile offsets are staged as 16 bits");
+static_assert(kTilePix == kGrainTilePix && kTileGrains == kGrainTileGrains &&
+                  kTileGroup == kGrainTileGroup,
+              "tile sizes the host sizes its buffers by");
 
 __device__ __forceinline__ uint32_t block_excl_scan_small(uint32_t v, uint32_t *s_wave,
                                                           uint32_t *total) {
@@ -2228,9 +2309,6 @@ uint32_t blocks_for(unsigned long long n, uint32_t max_blocks) {
 #define EMT_PERSISTENT_BLOCKS 2048
 #endif
 constexpr uint32_t kPersistentBlocks = EMT_PERSISTENT_BLOCKS;  // 8 blocks of 4 waves per CU
-#ifndef EMT_COUNT_BLOCKS
-#define EMT_COUNT_BLOCKS 1024
-#endif
 // the counting kernel's grid: one resident generation (4 workgroups per CU,
 // bound by its LDS and registers), so no workgroup waits for another's slot
 constexpr uint32_t kCountBlocks = EMT_COUNT_BLOCKS;
@@ -2253,7 +2331,7 @@ void launch_bin(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s)
     k_grid<<<(c.n_views + 63) / 64, 64, 0, s>>>(d.grids, d.desc, P);
     k_hist<<<grid, kBlock, 0, s>>>(d.xyz, d.grids, d.cell_of, d.rank, d.cell_count, d.desc);
     scan_excl(d.cell_count, &d.desc->n_cells_m1, c.n_cells, d.scan_part, d.cell_start, nullptr, s);
-    k_scatter<<<grid, kBlock, 0, s>>>(d.xyz, d.grids, d.cell_of, d.rank, d.cell_start, d.sg,
+    k_scatter<<<grid, kBlock, 0, s>>>(d.xyz, d.grids, d.cell_of, d.rank, d.cell_start, d.sg, d.sgf,
                                       d.desc);
 }
 

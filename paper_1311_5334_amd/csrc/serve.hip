@@ -56,6 +56,7 @@ struct emt_server {
     emt_config cfg{};
     std::vector<Pipe> pipes;
     uint32_t max_batch_views = 0;
+    unsigned long long max_batch_grains = 0;  // 0: no limit
     size_t pipe_budget = 0;
 
     std::mutex mu;
@@ -91,7 +92,9 @@ void account(emt_server *S, int delta) {
 }
 
 // Take waiting views for a free pipeline: arrival order, while the batch
-// fits the pipeline's HBM share. A view that alone exceeds it fails.
+// fits the pipeline's HBM share, its view limit and its grain limit (a view
+// larger than the grain limit goes alone). A view that alone exceeds the
+// HBM share fails.
 void form_batch(emt_server *S, Pipe &p, std::vector<Request *> &rejected) {
     p.batch.clear();
     unsigned long long n_total = 0;
@@ -99,6 +102,7 @@ void form_batch(emt_server *S, Pipe &p, std::vector<Request *> &rejected) {
     while (!S->queue.empty() && p.batch.size() < S->max_batch_views) {
         Request *r = S->queue.front();
         const unsigned long long nt = n_total + r->n;
+        if (S->max_batch_grains && !p.batch.empty() && nt > S->max_batch_grains) break;
         const uint32_t mn = std::max(max_n, r->n);
         const size_t need = emt::batch_bytes(p.ctx, nt, (uint32_t)p.batch.size() + 1, mn);
         if (need > S->pipe_budget) {
@@ -243,9 +247,19 @@ extern "C" {
 
 int emt_server_create(const emt_config *cfg, uint32_t n_pipes, uint32_t max_batch_views,
                       emt_server **out) {
+    emt_server_limits lim{};
+    lim.n_pipes = n_pipes;
+    lim.max_batch_views = max_batch_views;
+    lim.max_batch_grains = 0;
+    return emt_server_create2(cfg, &lim, out);
+}
+
+int emt_server_create2(const emt_config *cfg, const emt_server_limits *lim, emt_server **out) {
     if (!out) return EMT_EINVAL;
     *out = nullptr;
-    if (!cfg || n_pipes < 1 || n_pipes > kMaxPipes || max_batch_views < 1) return EMT_EINVAL;
+    if (!cfg || !lim) return EMT_EINVAL;
+    const uint32_t n_pipes = lim->n_pipes, max_batch_views = lim->max_batch_views;
+    if (n_pipes < 1 || n_pipes > kMaxPipes || max_batch_views < 1) return EMT_EINVAL;
     if (cfg->flags & EMT_F_DEVICE_PTRS) return EMT_EINVAL;  // submissions are host copies
     int rc = emt_validate(cfg, nullptr, 0);
     if (rc) return rc;
@@ -262,6 +276,7 @@ int emt_server_create(const emt_config *cfg, uint32_t n_pipes, uint32_t max_batc
     if (!S) return EMT_ENOMEM;
     S->cfg = *cfg;
     S->max_batch_views = max_batch_views;
+    S->max_batch_grains = lim->max_batch_grains;
     const size_t budget = cfg->hbm_budget ? (size_t)cfg->hbm_budget : (size_t)(0.8 * (double)free_b);
     S->pipe_budget = budget / n_pipes;
     S->pipes.resize(n_pipes);

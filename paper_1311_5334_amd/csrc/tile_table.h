@@ -1,0 +1,36 @@
+// tile_table.h -- queue sizes and launch shapes of the counting kernel and
+// the cell budget per grain, chosen by paper_1311_5334_amd/autotune.py
+// --tiles from timings of the whole path; -D on the compiler line overrides
+// each value.
+//   (hand-set starting values; not yet tuned)
+#ifndef EMT_TILE_TABLE_H
+#define EMT_TILE_TABLE_H
+
+#ifndef EMT_COUNT_PIECE
+#define EMT_COUNT_PIECE 4  // grains a flush lane tests per queue entry
+#endif
+#ifndef EMT_COUNT_LANE_PIECES
+#define EMT_COUNT_LANE_PIECES 8  // queue entries a lane adds per step
+#endif
+#ifndef EMT_COUNT_FETCH
+#define EMT_COUNT_FETCH 4  // cell pencils a lane fetches per step
+#endif
+#ifndef EMT_CHUNK_SEEDS
+#define EMT_CHUNK_SEEDS 128  // seeds a wave takes at a time (single views)
+#endif
+#ifndef EMT_COUNT_BLOCKS
+#define EMT_COUNT_BLOCKS 1024  // workgroups of the counting kernel
+#endif
+#ifndef EMT_CELLS_PER_GRAIN
+#define EMT_CELLS_PER_GRAIN 4  // cells a view may use per grain (plus 4096)
+#endif
+
+// queue capacities that follow from the above
+#ifndef EMT_COUNT_PIECE_CAP
+#define EMT_COUNT_PIECE_CAP (128 * EMT_COUNT_LANE_PIECES)
+#endif
+#ifndef EMT_COUNT_RUN_CAP
+#define EMT_COUNT_RUN_CAP (64 * EMT_COUNT_FETCH)
+#endif
+
+#endif

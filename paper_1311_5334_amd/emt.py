@@ -16,13 +16,14 @@ LIB_PATH = os.path.join(HERE, "libemt.so")
 
 EMT_ABI_VERSION = 2
 EMT_OK, EMT_EINVAL, EMT_ERANGE, EMT_ENOMEM, EMT_EDEVICE, EMT_EOVERFLOW = 0, -1, -2, -3, -4, -5
-EMT_F_STATS, EMT_F_FP64_FIT_ALWAYS, EMT_F_DEVICE_PTRS = 0x1, 0x2, 0x4
+EMT_F_STATS, EMT_F_FP64_FIT_ALWAYS, EMT_F_DEVICE_PTRS, EMT_F_CANDIDATES = 0x1, 0x2, 0x4, 0x8
 STAGES = ("stage", "bin", "seed", "count", "members", "merge", "fit", "out")
 EMT_N_STAGES = len(STAGES)
 EXPORTS = ("emt_default_config", "emt_validate", "emt_create", "emt_track_views",
            "emt_last_stats", "emt_destroy", "emt_strerror", "emt_server_create",
            "emt_server_submit", "emt_server_poll", "emt_server_get_stats",
-           "emt_server_destroy", "emt_find_grains", "emt_filter_stack")
+           "emt_server_destroy", "emt_find_grains", "emt_filter_stack",
+           "emt_view_candidates", "emt_server_create2")
 # the paper's view (300 x 250 x 50 um) at 1280 x 1024 x 40 pixels: pitches
 # in 0.01 um units as exact fractions
 PAPER_PITCH_NUM, PAPER_PITCH_DEN = (375, 3125, 125), (16, 128, 1)
@@ -82,6 +83,11 @@ class EmtServed(C.Structure):
                 ("t_done_ms", C.c_double)]
 
 
+class EmtServerLimits(C.Structure):
+    _fields_ = [("n_pipes", C.c_uint32), ("max_batch_views", C.c_uint32),
+                ("max_batch_grains", C.c_uint64)]
+
+
 class EmtServerStats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("batches", C.c_uint64),
                 ("max_batch_views_seen", C.c_uint32), ("n_pipes", C.c_uint32),
@@ -123,6 +129,10 @@ def load(path: str = LIB_PATH):
     lib.emt_track_views.argtypes = [C.c_void_p, C.POINTER(EmtViewIn), C.c_uint32,
                                     C.POINTER(EmtViewOut)]
     lib.emt_track_views.restype = C.c_int
+    lib.emt_view_candidates.argtypes = [C.c_void_p, C.c_uint32,
+                                        C.POINTER(C.POINTER(C.c_uint32)),
+                                        C.POINTER(C.c_uint32)]
+    lib.emt_view_candidates.restype = C.c_int
     lib.emt_last_stats.argtypes = [C.c_void_p, C.POINTER(EmtCallStats)]
     lib.emt_last_stats.restype = C.c_int
     lib.emt_destroy.argtypes = [C.c_void_p]
@@ -132,6 +142,9 @@ def load(path: str = LIB_PATH):
     lib.emt_server_create.argtypes = [C.POINTER(EmtConfig), C.c_uint32, C.c_uint32,
                                       C.POINTER(C.c_void_p)]
     lib.emt_server_create.restype = C.c_int
+    lib.emt_server_create2.argtypes = [C.POINTER(EmtConfig), C.POINTER(EmtServerLimits),
+                                       C.POINTER(C.c_void_p)]
+    lib.emt_server_create2.restype = C.c_int
     lib.emt_server_submit.argtypes = [C.c_void_p, C.POINTER(EmtViewIn), C.POINTER(C.c_uint64)]
     lib.emt_server_submit.restype = C.c_int
     lib.emt_server_poll.argtypes = [C.c_void_p, C.POINTER(EmtServed), C.c_uint32,
@@ -329,6 +342,19 @@ def emt_filter_stack(ctx, raw, gain, thr, device_ptrs: bool = False, out=None):
     return res
 
 
+def emt_view_candidates(ctx, view: int) -> np.ndarray:
+    """Candidates (i, j, n) of one view of the last call, as a (K, 3) uint32
+    array in the device's list order (the context needs EMT_F_CANDIDATES)."""
+    p = C.POINTER(C.c_uint32)()
+    n = C.c_uint32()
+    rc = load().emt_view_candidates(ctx, view, C.byref(p), C.byref(n))
+    if rc != EMT_OK:
+        raise EmtError(rc, "emt_view_candidates")
+    if n.value == 0:
+        return np.zeros((0, 3), np.uint32)
+    return np.ctypeslib.as_array(p, shape=(3 * n.value,)).reshape(-1, 3).copy()
+
+
 def emt_last_stats(ctx) -> dict:
     st = EmtCallStats()
     rc = load().emt_last_stats(ctx, C.byref(st))
@@ -358,6 +384,9 @@ class Tracker:
     def stats(self) -> dict:
         return emt_last_stats(self.ctx)
 
+    def candidates(self, view: int = 0) -> np.ndarray:
+        return emt_view_candidates(self.ctx, view)
+
     def find_grains(self, stack, threshold: int, **kw):
         return emt_find_grains(self.ctx, stack, threshold, self.device_ptrs, **kw)
 
@@ -386,10 +415,12 @@ class Server:
     """The served form: ``submit`` views as they arrive, ``poll`` finished
     ones. Wraps emt_server_* (argument marshalling only)."""
 
-    def __init__(self, n_pipes: int = 2, max_batch_views: int = 64, **cfg):
+    def __init__(self, n_pipes: int = 2, max_batch_views: int = 64, max_batch_grains: int = 0,
+                 **cfg):
         self.cfg = emt_default_config(**cfg)
         h = C.c_void_p()
-        rc = load().emt_server_create(C.byref(self.cfg), n_pipes, max_batch_views, C.byref(h))
+        lim = EmtServerLimits(n_pipes, max_batch_views, max_batch_grains)
+        rc = load().emt_server_create2(C.byref(self.cfg), C.byref(lim), C.byref(h))
         if rc != EMT_OK:
             raise EmtError(rc, "emt_server_create")
         self.h = h

@@ -328,3 +328,39 @@ def make_degenerate_view(p=(20000, 20000, 2000), q_offset=(1000, 0, 0),
     line = [Q + (m + shift) * D for m in range(-half, n_line - half)]
     return np.concatenate([np.repeat(P[None, :], n_copies, axis=0),
                            np.array(line, np.int64)]).astype(np.int32)
+
+
+def make_c4_fixed(index: int, side_um: float, fog_per_1000_um3: float) -> View:
+    """A served-mix view of a given size and fog (e.g. the largest and
+    foggiest, 350 x 350 um at 10 per 1000 um^3), otherwise as make_c4."""
+    seed = view_seed(4, 100000 + index)
+    rng = _rng(seed)
+    n_tracks = int(round(2449.0 * side_um * side_um * 1e-6))
+    box = np.array([side_um, side_um, THICKNESS_UM])
+    segs = _tracks_mixed(rng, box, n_tracks)
+    return _assemble(rng, box, segs, fog_per_1000_um3 * 1e-3, "c4", seed)
+
+
+SPAN_MAX = 1 << 18
+
+
+def make_far_line_view(d, n_far: int = 9, offsets=((0, 0, 70), (0, 70, 0), (70, 0, 0),
+                                                   (0, 52, 50), (50, 0, 52), (45, 55, 0),
+                                                   (0, 0, 95), (60, -60, 0), (-40, 0, 41))):
+    """Units, int32: a seed pair a few units apart (g0, g0 + d) and, near the
+    far end of the largest span a view may have (2^18 units per axis),
+    n_far grains exactly on the line g0 + m d and grains displaced from it by
+    the given offsets, some within and some beyond 0.5 um of the line. The
+    pair's line must be followed across the whole view to count them."""
+    d = np.asarray(d, np.int64)
+    base = np.where(d >= 0, 1000, SPAN_MAX - 1000).astype(np.int64)
+    nz = np.abs(d) > 0
+    M = int(np.min((SPAN_MAX - 2400) // np.abs(d[nz])))
+    pts = [base, base + d]
+    steps = [M - 53 * k for k in range(n_far)]
+    pts += [base + m * d for m in steps]
+    for k, off in enumerate(offsets):
+        pts.append(base + (M - 29 * k - 11) * d + np.asarray(off, np.int64))
+    xyz = np.array(pts, np.int64)
+    assert xyz.min() >= 0 and xyz.max() < SPAN_MAX
+    return xyz.astype(np.int32)

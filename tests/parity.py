@@ -48,3 +48,16 @@ def assert_view_parity(xyz, got: dict, ref, check_fit: bool = True) -> None:
         assert np.all(np.abs(g["centroid"] - c_ref) <= tol), (k, g["centroid"], c_ref)
         assert abs(float(g["t_begin"]) - rt["t_begin"]) <= 1e-3, k
         assert abs(float(g["t_end"]) - rt["t_end"]) <= 1e-3, k
+
+
+def assert_candidates_equal(got_ijn, ref) -> None:
+    """Candidate lists element by element: the device's list (any order)
+    sorted into the priority order (n descending, then i, j) must equal the
+    oracle's (i, j, n) list exactly."""
+    g = np.asarray(got_ijn, np.int64).reshape(-1, 3)
+    order = np.lexsort((g[:, 1], g[:, 0], -g[:, 2]))
+    g = g[order]
+    r = np.asarray(ref.cand, np.int64).reshape(-1, 3)
+    assert g.shape == r.shape, (g.shape, r.shape)
+    bad = np.nonzero(np.any(g != r, axis=1))[0]
+    assert len(bad) == 0, (bad[:5], g[bad[:5]], r[bad[:5]])

@@ -24,7 +24,7 @@ def emt():
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(emt_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(emt_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_function(emt):
@@ -32,7 +32,7 @@ def test_library_exports_every_declared_function(emt):
     assert set(names) == set(emt.EXPORTS)
     out = subprocess.run(["nm", "-D", "--defined-only", emt.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
-    exported = set(re.findall(r" T (emt_[a-z_]+)", out))
+    exported = set(re.findall(r" T (emt_[a-z0-9_]+)", out))
     for n in names:
         assert n in exported, n
         assert hasattr(emt.load(), n)
@@ -47,7 +47,8 @@ def test_struct_layout_matches_header(emt):
 #define O(t, f) printf(#t "." #f " %zu\n", offsetof(t, f));
 int main(void) {
   S(emt_config) S(emt_view_in) S(emt_track) S(emt_view_stats) S(emt_view_out) S(emt_call_stats)
-  S(emt_served) S(emt_server_stats) S(emt_stack_geom)
+  S(emt_served) S(emt_server_stats) S(emt_stack_geom) S(emt_server_limits)
+  O(emt_server_limits, max_batch_grains)
   O(emt_stack_geom, threshold) O(emt_stack_geom, pitch_den)
   O(emt_config, hbm_budget) O(emt_config, stream) O(emt_config, cyl_ext)
   O(emt_config, thr_slope) O(emt_config, thr_max) O(emt_track, slope) O(emt_track, t_end)
@@ -81,6 +82,8 @@ int main(void) {
         "emt_call_stats.ms_total": emt.EmtCallStats.ms_total.offset,
         "emt_served": C.sizeof(emt.EmtServed), "emt_server_stats": C.sizeof(emt.EmtServerStats),
         "emt_stack_geom": C.sizeof(emt.EmtStackGeom),
+        "emt_server_limits": C.sizeof(emt.EmtServerLimits),
+        "emt_server_limits.max_batch_grains": emt.EmtServerLimits.max_batch_grains.offset,
         "emt_stack_geom.threshold": emt.EmtStackGeom.threshold.offset,
         "emt_stack_geom.pitch_den": emt.EmtStackGeom.pitch_den.offset,
         "emt_served.tracks": emt.EmtServed.tracks.offset,

@@ -419,3 +419,46 @@ def test_seed_total_above_2_32_is_an_overflow(emt):
     with emt.Tracker(device=0) as t2:
         ref = t2([small])[0]
     assert again["tracks"].tobytes() == ref["tracks"].tobytes()
+
+
+def _with_candidates(emt, xyz, **cfg):
+    with emt.Tracker(device=0, flags=emt.EMT_F_CANDIDATES, **cfg) as t:
+        got = t([xyz])[0]
+        cands = t.candidates(0)
+    return got, cands
+
+
+@pytest.mark.parametrize("which", ["c1-0", "c1-1", "c2-0", "c5-crop"])
+def test_candidate_lists_match_oracle(emt, oracle_mod, which):
+    """Every candidate (i, j, n), i.e. the count n(s) of every seed that
+    reaches the threshold, element by element against the oracle."""
+    from parity import assert_candidates_equal
+    if which.startswith("c1"):
+        xyz = synth.make_c1(int(which[-1])).xyz
+    elif which == "c2-0":
+        xyz = synth.make_c2(0).xyz
+    else:
+        x = synth.make_c5(5).xyz
+        lo = np.array([10000, 10000, -1000])
+        xyz = x[np.all((x >= lo) & (x < lo + np.array([12000, 12000, 7000])), axis=1)]
+    _say(f"candidates {which}: {len(xyz)} grains")
+    ref = oracle_mod.track_view(xyz)
+    got, cands = _with_candidates(emt, xyz)
+    assert got["n_candidates"] == len(cands)
+    assert_candidates_equal(cands, ref)
+    assert_view_parity(xyz, got, ref)
+
+
+def test_candidate_lists_in_a_batch(emt, oracle_mod):
+    from parity import assert_candidates_equal
+    views = [synth.make_c1(i).xyz for i in (4, 5, 6)] + [np.zeros((0, 3), np.int32)]
+    with emt.Tracker(device=0, flags=emt.EMT_F_CANDIDATES, min_grains=6) as t:
+        t(views)
+        for k, x in enumerate(views):
+            assert_candidates_equal(t.candidates(k), oracle_mod.track_view(x, n_min=6))
+        with pytest.raises(emt.EmtError):
+            t.candidates(len(views))
+    with emt.Tracker(device=0) as t:
+        t(views[:1])
+        with pytest.raises(emt.EmtError):
+            t.candidates(0)
