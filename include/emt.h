@@ -365,6 +365,28 @@ int emt_server_get_stats(emt_server *srv, emt_server_stats *stats);
  * Views still waiting are dropped. NULL is ignored. */
 void emt_server_destroy(emt_server *srv);
 
+/*
+ * Measured device rates, the denominators beside the specification's for
+ * the roofline of each kernel: the counting test is 32-bit integer and FP32
+ * lane work (paper Sec. 3: tracking is most of the time), binning and the
+ * image steps stream HBM. Each rate is the fastest of five timed launches of
+ * a kernel that does nothing else: chains of 24-bit integer multiply-adds,
+ * chains of FP32 FMAs (one lane operation each, not packed), 128-bit LDS
+ * reads, and a 1 GiB device-to-device copy (bytes read plus written).
+ * Allocates 2 GiB of device memory for the call. Returns EMT_OK,
+ * EMT_EINVAL (NULL out or no such device) or EMT_EDEVICE.
+ */
+typedef struct {
+    double int_lane_ops;   /* 32-bit integer lane operations per second   */
+    double fp32_lane_ops;  /* FP32 FMA lane operations per second         */
+    double lds_bytes;      /* LDS bytes read per second, whole device     */
+    double hbm_copy_bytes; /* HBM bytes read plus written per second      */
+    uint32_t compute_units;
+    uint32_t clock_khz;    /* peak engine clock the runtime reports       */
+} emt_peaks;
+
+int emt_measure_peaks(int32_t device, emt_peaks *out);
+
 #ifdef __cplusplus
 }
 #endif

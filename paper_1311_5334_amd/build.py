@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libemt.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "api.hip", "serve.hip"]
+SOURCES = ["kernels.hip", "api.hip", "serve.hip", "peaks.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",

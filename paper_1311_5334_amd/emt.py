@@ -23,7 +23,7 @@ EXPORTS = ("emt_default_config", "emt_validate", "emt_create", "emt_track_views"
            "emt_last_stats", "emt_destroy", "emt_strerror", "emt_server_create",
            "emt_server_submit", "emt_server_poll", "emt_server_get_stats",
            "emt_server_destroy", "emt_find_grains", "emt_filter_stack",
-           "emt_view_candidates", "emt_server_create2")
+           "emt_view_candidates", "emt_server_create2", "emt_measure_peaks")
 # the paper's view (300 x 250 x 50 um) at 1280 x 1024 x 40 pixels: pitches
 # in 0.01 um units as exact fractions
 PAPER_PITCH_NUM, PAPER_PITCH_DEN = (375, 3125, 125), (16, 128, 1)
@@ -95,6 +95,12 @@ class EmtServerStats(C.Structure):
                 ("elapsed_ms", C.c_double)]
 
 
+class EmtPeaks(C.Structure):
+    _fields_ = [("int_lane_ops", C.c_double), ("fp32_lane_ops", C.c_double),
+                ("lds_bytes", C.c_double), ("hbm_copy_bytes", C.c_double),
+                ("compute_units", C.c_uint32), ("clock_khz", C.c_uint32)]
+
+
 TRACK_DTYPE = np.dtype([("seed", "<u4", (2,)), ("grain_offset", "<u4"), ("n_grains", "<u4"),
                         ("axis", "<u4"), ("fit_fp64", "<u4"), ("degenerate", "<u4"),
                         ("slope", "<f4", (2,)), ("dir", "<f4", (3,)),
@@ -160,8 +166,20 @@ def load(path: str = LIB_PATH):
     lib.emt_filter_stack.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(EmtStackGeom), C.c_void_p,
                                      C.c_void_p, C.c_void_p]
     lib.emt_filter_stack.restype = C.c_int
+    lib.emt_measure_peaks.argtypes = [C.c_int32, C.POINTER(EmtPeaks)]
+    lib.emt_measure_peaks.restype = C.c_int
     _lib = lib
     return lib
+
+
+def emt_measure_peaks(device: int = 0) -> dict:
+    """Measured int32 and FP32 lane-operation rates, LDS read bandwidth and
+    HBM copy bandwidth of one device (emt_measure_peaks)."""
+    pk = EmtPeaks()
+    rc = load().emt_measure_peaks(device, C.byref(pk))
+    if rc != 0:
+        raise EmtError(rc, "emt_measure_peaks")
+    return {f: getattr(pk, f) for f, _ in EmtPeaks._fields_}
 
 
 def emt_strerror(rc: int) -> str:

@@ -47,7 +47,8 @@ def test_struct_layout_matches_header(emt):
 #define O(t, f) printf(#t "." #f " %zu\n", offsetof(t, f));
 int main(void) {
   S(emt_config) S(emt_view_in) S(emt_track) S(emt_view_stats) S(emt_view_out) S(emt_call_stats)
-  S(emt_served) S(emt_server_stats) S(emt_stack_geom) S(emt_server_limits)
+  S(emt_served) S(emt_server_stats) S(emt_stack_geom) S(emt_server_limits) S(emt_peaks)
+  O(emt_peaks, hbm_copy_bytes) O(emt_peaks, clock_khz)
   O(emt_server_limits, max_batch_grains)
   O(emt_stack_geom, threshold) O(emt_stack_geom, pitch_den)
   O(emt_config, hbm_budget) O(emt_config, stream) O(emt_config, cyl_ext)
@@ -83,6 +84,9 @@ int main(void) {
         "emt_served": C.sizeof(emt.EmtServed), "emt_server_stats": C.sizeof(emt.EmtServerStats),
         "emt_stack_geom": C.sizeof(emt.EmtStackGeom),
         "emt_server_limits": C.sizeof(emt.EmtServerLimits),
+        "emt_peaks": C.sizeof(emt.EmtPeaks),
+        "emt_peaks.hbm_copy_bytes": emt.EmtPeaks.hbm_copy_bytes.offset,
+        "emt_peaks.clock_khz": emt.EmtPeaks.clock_khz.offset,
         "emt_server_limits.max_batch_grains": emt.EmtServerLimits.max_batch_grains.offset,
         "emt_stack_geom.threshold": emt.EmtStackGeom.threshold.offset,
         "emt_stack_geom.pitch_den": emt.EmtStackGeom.pitch_den.offset,
