@@ -254,6 +254,27 @@ int emt_find_grains(emt_ctx *ctx, const uint8_t *stack,
                     uint32_t max_out, uint32_t *n_out);
 
 /*
+ * emt_find_grains without any allocation, for callers that cannot allocate
+ * device or host memory during the call (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc). Same computation,
+ * arguments, results and return codes as emt_find_grains on a context
+ * created with EMT_F_DEVICE_PTRS (stack and xyz_out are device pointers;
+ * a context without the flag gives EMT_EINVAL). The working buffers
+ * (per-tile counts, per-group sums, staging) live in one static device
+ * array of EMT_NOALLOC_SCRATCH_BYTES per device, which the library holds
+ * from emt_create until the process ends; a stack needing more (about one
+ * byte per pixel: up to ~67 M pixels, e.g. 1280 x 1024 x 51 frames) gives
+ * EMT_ERANGE before any work. Every call on one device shares that array:
+ * calls that overlap on a device race and must not be made (one call at a
+ * time per device, across all contexts and threads).
+ */
+#define EMT_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+int emt_find_grains_noalloc(emt_ctx *ctx, const uint8_t *stack,
+                            const emt_stack_geom *geom, int32_t *xyz_out,
+                            uint32_t max_out, uint32_t *n_out);
+
+/*
  * Image filtering (paper, Sec. 2, image processing paragraph; Fig. 3a, 3b):
  * the step before grain recognition. The camera's pixels differ in gain, so
  * each camera pixel (x, y) has its own gain correction and threshold, used

@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -606,6 +607,49 @@ int batch_caps(const emt_ctx *ctx, unsigned long long n_total, uint32_t n_views,
     return EMT_OK;
 }
 
+// Scratch of emt_find_grains_noalloc: the per-tile grain counts, per-group
+// sums, staging slots and the grain total of one recognition call, carved
+// in that order (1 byte a stack pixel plus ~0.1 %). One copy per device,
+// held until the process ends; every call on a device shares it and keeps
+// the last call's contents (the per-group sums, the only words read before
+// they are written, are cleared by a kernel at the start of each call).
+// Host code never passes the array's name to a kernel: it uses the device
+// address emt_create resolves for each device (scratch_dev).
+constexpr size_t kNoAllocScratchBytes = (size_t)EMT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxScratchDevices = 256;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxScratchDevices];  // address of scratch on each device
+
+// With the device current: resolve the array's address on it (once).
+int resolve_scratch(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return EMT_OK;  // variant unavailable
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[device]) return EMT_OK;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return EMT_EDEVICE;
+    }
+    g_scratch_dev[device] = ptr;
+    return EMT_OK;
+}
+
+void *scratch_dev(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_dev[device];
+}
+
+// Bytes the recognition buffers take when carved from one block.
+size_t grain_scratch_bytes(const StackGeom &G) {
+    auto r = [](size_t b) { return ((b + 255) / 256) * 256; };
+    return r(bytes_of<uint32_t>(grain_tile_count(G))) +
+           r(bytes_of<uint32_t>(grain_group_count(G))) +
+           r(bytes_of<uint16_t>(grain_stage_slots(G))) + r(bytes_of<uint32_t>(1));
+}
+
 }  // namespace
 
 extern "C" {
@@ -716,6 +760,17 @@ int emt_create(const emt_config *cfg, emt_ctx **out) {
     if (hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming) != hipSuccess) {
         emt_destroy(ctx);
         return EMT_EDEVICE;
+    }
+    // set-up of the no-allocation variant: the scratch array's address on
+    // this device, and the pinned words results come back through
+    if ((rc = resolve_scratch(cfg->device)) != EMT_OK) {
+        emt_destroy(ctx);
+        return rc;
+    }
+    size_t small_cap = 0;
+    if ((rc = pinned(ctx, ctx->h_small, small_cap, 4)) != EMT_OK) {
+        emt_destroy(ctx);
+        return rc;
     }
     *out = ctx;
     return EMT_OK;
@@ -917,8 +972,13 @@ int emt_track_views(emt_ctx *ctx, const emt_view_in *views, uint32_t n_views, em
     return rc;
 }
 
+
+// static_buf: null for emt_find_grains (buffers from the context's arena,
+// grown as needed); the device address of scratch for the no-allocation
+// variant (device pointers only, no allocation, stacks up to its size).
 static int find_grains_impl(emt_ctx *ctx, const uint8_t *stack, const emt_stack_geom *g,
-                            int32_t *xyz_out, uint32_t max_out, uint32_t *n_out) {
+                            int32_t *xyz_out, uint32_t max_out, uint32_t *n_out,
+                            void *static_buf = nullptr) {
     if (!ctx || !g || !n_out) return EMT_EINVAL;
     *n_out = 0;
     if (ctx->poisoned) return EMT_EDEVICE;
@@ -954,14 +1014,23 @@ static int find_grains_impl(emt_ctx *ctx, const uint8_t *stack, const emt_stack_
     G.inv_nx = 1.0 / (double)G.nx;
     G.inv_ny = 1.0 / (double)G.ny;
     const size_t nt = grain_tile_count(G), ng = grain_group_count(G);
-    const size_t bytes = (dev ? 0 : bytes_of<uint8_t>((size_t)npix)) + bytes_of<uint32_t>(nt) +
-                         bytes_of<uint32_t>(ng) + bytes_of<uint16_t>(grain_stage_slots(G)) +
-                         bytes_of<uint32_t>(1) + (dev ? 0 : bytes_of<int32_t>(3 * (size_t)max_out));
-    int rc;
-    if ((rc = arena(ctx, ctx->stack_buf, bytes))) return rc;
-    size_t cap = 0;
-    if (!ctx->h_small && (rc = pinned(ctx, ctx->h_small, cap, 4))) return rc;
-    char *p = (char *)ctx->stack_buf.p;
+    char *p = nullptr;
+    if (static_buf) {
+        if (!dev) return EMT_EINVAL;
+        if (grain_scratch_bytes(G) > kNoAllocScratchBytes) return EMT_ERANGE;
+        if (!ctx->h_small) return EMT_EDEVICE;  // made by emt_create
+        p = (char *)static_buf;
+    } else {
+        const size_t bytes = (dev ? 0 : bytes_of<uint8_t>((size_t)npix)) + bytes_of<uint32_t>(nt) +
+                             bytes_of<uint32_t>(ng) + bytes_of<uint16_t>(grain_stage_slots(G)) +
+                             bytes_of<uint32_t>(1) +
+                             (dev ? 0 : bytes_of<int32_t>(3 * (size_t)max_out));
+        int rc;
+        if ((rc = arena(ctx, ctx->stack_buf, bytes))) return rc;
+        size_t cap = 0;
+        if (!ctx->h_small && (rc = pinned(ctx, ctx->h_small, cap, 4))) return rc;
+        p = (char *)ctx->stack_buf.p;
+    }
     const uint8_t *img = stack;
     if (!dev) img = carve<uint8_t>(p, (size_t)npix);
     GrainBufs b{};
@@ -1055,6 +1124,19 @@ int emt_filter_stack(emt_ctx *ctx, const uint8_t *raw, const emt_stack_geom *geo
 int emt_find_grains(emt_ctx *ctx, const uint8_t *stack, const emt_stack_geom *geom,
                     int32_t *xyz_out, uint32_t max_out, uint32_t *n_out) {
     const int rc = find_grains_impl(ctx, stack, geom, xyz_out, max_out, n_out);
+    (void)hipGetLastError();
+    return rc;
+}
+
+int emt_find_grains_noalloc(emt_ctx *ctx, const uint8_t *stack, const emt_stack_geom *geom,
+                            int32_t *xyz_out, uint32_t max_out, uint32_t *n_out) {
+    if (!ctx || !n_out) return EMT_EINVAL;
+    void *buf = scratch_dev(ctx->cfg.device);
+    if (!buf) {
+        *n_out = 0;
+        return EMT_EINVAL;
+    }
+    const int rc = find_grains_impl(ctx, stack, geom, xyz_out, max_out, n_out, buf);
     (void)hipGetLastError();
     return rc;
 }

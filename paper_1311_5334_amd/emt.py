@@ -23,7 +23,8 @@ EXPORTS = ("emt_default_config", "emt_validate", "emt_create", "emt_track_views"
            "emt_last_stats", "emt_destroy", "emt_strerror", "emt_server_create",
            "emt_server_submit", "emt_server_poll", "emt_server_get_stats",
            "emt_server_destroy", "emt_find_grains", "emt_filter_stack",
-           "emt_view_candidates", "emt_server_create2", "emt_measure_peaks")
+           "emt_view_candidates", "emt_server_create2", "emt_measure_peaks",
+           "emt_find_grains_noalloc")
 # the paper's view (300 x 250 x 50 um) at 1280 x 1024 x 40 pixels: pitches
 # in 0.01 um units as exact fractions
 PAPER_PITCH_NUM, PAPER_PITCH_DEN = (375, 3125, 125), (16, 128, 1)
@@ -166,6 +167,8 @@ def load(path: str = LIB_PATH):
     lib.emt_filter_stack.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(EmtStackGeom), C.c_void_p,
                                      C.c_void_p, C.c_void_p]
     lib.emt_filter_stack.restype = C.c_int
+    lib.emt_find_grains_noalloc.argtypes = lib.emt_find_grains.argtypes
+    lib.emt_find_grains_noalloc.restype = C.c_int
     lib.emt_measure_peaks.argtypes = [C.c_int32, C.POINTER(EmtPeaks)]
     lib.emt_measure_peaks.restype = C.c_int
     _lib = lib
