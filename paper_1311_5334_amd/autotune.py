@@ -7,18 +7,23 @@ density with every candidate cell geometry, and write the fastest into
 decided by the exact test); only the work does: small cells mean more cell
 runs per seed line, large cells more grains tested per hit.
 
-Tiles (``--tiles``): the counting kernel's queue and launch shapes and the
-cells allowed per grain are compile-time constants. Each candidate value is
-built into a library of its own (``build.build`` with -D overrides, in a
-temporary directory) and timed in a child process on three workloads (one
-c2 view, 8 c5 views and 16 c3 views per call); coordinate descent keeps the
-value that lowers the sum of the workloads' times relative to the starting
-tiles, and the result is written into ``csrc/tile_table.h``.
+Tiles: the counting kernel's queue sizes, workgroup shape and refill size
+and the cells allowed per grain are compile-time constants. ``--build-tiles
+DIR`` (no GPU needed) builds the starting tiles and every one-at-a-time
+variation of them into libraries of their own under DIR (``build.build``
+with -D overrides). ``--tiles --prebuilt DIR`` (on the GPU) times each of
+them in a child process on three workloads (one c2 view, 8 c5 views and 16
+c3 views per call), keeps for each constant the value that lowers the mean
+of the workloads' times relative to the starting tiles, and writes the
+combination into ``csrc/tile_table.h``; a second ``--build-tiles`` then
+builds variations around it.
 
-    python -m paper_1311_5334_amd.autotune [--cells | --tiles] [--report PATH]
+    python -m paper_1311_5334_amd.autotune [--cells] [--report PATH]
+    python -m paper_1311_5334_amd.autotune --build-tiles DIR
+    python -m paper_1311_5334_amd.autotune --tiles --prebuilt DIR [--report PATH]
 
-Both rewrite a header: rebuild the library afterwards. Needs a GPU. Prints a
-line per timed candidate as it goes.
+Cells and tiles rewrite a header: rebuild the library afterwards. Timing
+needs a GPU and prints a line per timed candidate as it goes.
 """
 from __future__ import annotations
 
@@ -89,17 +94,19 @@ constexpr int kTunedCells[8][3] = {{
 TILE_TABLE = os.path.join(HERE, "csrc", "tile_table.h")
 # candidate values of each tile constant (see csrc/tile_table.h)
 TILE_SPACE = {
-    "EMT_COUNT_PIECE": (2, 3, 4, 6),
-    "EMT_COUNT_LANE_PIECES": (4, 8, 12),
-    "EMT_COUNT_FETCH": (2, 3, 4, 6),
+    "EMT_COUNT_PIECE": (1, 2, 4),
+    "EMT_COUNT_LANE_PIECES": (8, 16),
+    "EMT_COUNT_FETCH": (2, 3, 4),
+    "EMT_COUNT_REFILL": (16, 32, 48),
     "EMT_CHUNK_SEEDS": (64, 128, 256),
     "EMT_COUNT_BLOCKS": (1024, 2048),
-    "EMT_CELLS_PER_GRAIN": (4, 8, 16),
+    "EMT_CELLS_PER_GRAIN": (4, 8),
 }
 TILE_COMMENTS = {
     "EMT_COUNT_PIECE": "grains a flush lane tests per queue entry",
     "EMT_COUNT_LANE_PIECES": "queue entries a lane adds per step",
     "EMT_COUNT_FETCH": "cell pencils a lane fetches per step",
+    "EMT_COUNT_REFILL": "lanes waiting for a seed before a wave refills",
     "EMT_CHUNK_SEEDS": "seeds a wave takes at a time (single views)",
     "EMT_COUNT_BLOCKS": "workgroups of the counting kernel",
     "EMT_CELLS_PER_GRAIN": "cells a view may use per grain (plus 4096)",
@@ -177,78 +184,98 @@ def time_library(lib: str, views_path: str, calls: int = 3) -> dict:
     return out
 
 
-def tune_tiles(report: str | None, passes: int = 2) -> int:
+def _tag(tiles: dict) -> str:
+    return "_".join(f"{k[4:].lower()}{v}" for k, v in sorted(tiles.items()))
+
+
+def tile_candidates(start: dict) -> list:
+    """The starting tiles and every one-at-a-time variation of them."""
+    out = [dict(start)]
+    for k, values in TILE_SPACE.items():
+        for v in values:
+            if v != start[k]:
+                out.append(dict(start, **{k: v}))
+    return out
+
+
+def build_tiles(outdir: str) -> int:
+    """CPU step: build each candidate into outdir/<tag>/libemt.so, and list
+    them in outdir/candidates.json."""
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_1311_5334_amd import build
+    os.makedirs(outdir, exist_ok=True)
+    cands = tile_candidates(read_tiles())
+
+    def one(tiles):
+        d = os.path.join(outdir, _tag(tiles))
+        build.build(lib=os.path.join(d, "libemt.so"), defines=tiles, objdir=os.path.join(d, "obj"))
+        print("built", _tag(tiles), flush=True)
+        return {"tiles": tiles, "lib": os.path.join(_tag(tiles), "libemt.so")}
+
+    with ThreadPoolExecutor(4) as ex:
+        listed = list(ex.map(one, cands))
+    json.dump(listed, open(os.path.join(outdir, "candidates.json"), "w"), indent=1)
+    return 0
+
+
+def tune_tiles(prebuilt: str, report: str | None) -> int:
+    """GPU step: time the prebuilt candidates; per constant keep the value
+    with the lowest mean time ratio against the starting tiles."""
     import subprocess
     import tempfile
-    from paper_1311_5334_amd import build
+    listed = json.load(open(os.path.join(prebuilt, "candidates.json")))
     tmp = tempfile.mkdtemp(prefix="emt_tiles_")
     views_path = os.path.join(tmp, "views.npz")
     _workload_views(views_path)
-    cache = {}
     t_start = time.time()
-
-    def timed(tiles: dict) -> dict:
-        key = tuple(sorted(tiles.items()))
-        if key in cache:
-            return cache[key]
-        tag = "_".join(str(v) for _, v in key)
-        lib = os.path.join(tmp, f"libemt_{tag}.so")
-        build.build(lib=lib, defines=tiles, objdir=os.path.join(tmp, "obj_" + tag))
+    times = []
+    for item in listed:
+        lib = os.path.join(prebuilt, item["lib"])
         r = subprocess.run([sys.executable, "-m", "paper_1311_5334_amd.autotune",
                             "--time-lib", lib, views_path], capture_output=True, text=True,
                            timeout=600)
         if r.returncode != 0:
             sys.stderr.write(r.stdout[-2000:] + r.stderr[-2000:])
-            raise RuntimeError(f"timing of {tag} failed")
+            raise RuntimeError(f"timing of {item['lib']} failed")
         res = json.loads(r.stdout.strip().splitlines()[-1])
-        cache[key] = res
-        print(f"  {dict(key)}: " + ", ".join(f"{k} {v:.3f} ms" for k, v in res.items()) +
+        times.append((item["tiles"], res))
+        print(f"  {item['tiles']}: " + ", ".join(f"{k} {v:.3f} ms" for k, v in res.items()) +
               f" [{time.time() - t_start:.0f} s]", flush=True)
-        return res
-
-    start = read_tiles()
-    base = timed(start)
+    start, base = times[0]
 
     def score(res: dict) -> float:
         return sum(res[w] / base[w] for w in WORKLOADS) / len(WORKLOADS)
 
-    cur = dict(start)
-    for _ in range(passes):
-        changed = False
-        for k, values in TILE_SPACE.items():
-            best_v, best_s = cur[k], score(timed(cur))
-            for v in values:
-                trial = dict(cur, **{k: v})
-                sc = score(timed(trial))
-                if sc < best_s - 0.005:
-                    best_v, best_s = v, sc
-            if best_v != cur[k]:
-                cur[k] = best_v
-                changed = True
-        if not changed:
-            break
-    final = timed(cur)
+    chosen = dict(start)
+    for k in TILE_SPACE:
+        best_v, best_s = start[k], 1.0
+        for tiles, res in times:
+            diff = [m for m in tiles if tiles[m] != start[m]]
+            if diff == [k] and score(res) < best_s - 0.01:
+                best_v, best_s = tiles[k], score(res)
+        chosen[k] = best_v
     lines = [f"starting tiles {start}: " + ", ".join(f"{w} {base[w]:.3f} ms" for w in WORKLOADS),
-             f"chosen tiles {cur}: " + ", ".join(f"{w} {final[w]:.3f} ms" for w in WORKLOADS) +
-             f" (mean time ratio {score(final):.3f})",
-             f"{len(cache)} builds timed"]
-    write_tiles(TILE_TABLE, cur, "\n".join("//   " + ln for ln in lines))
+             f"chosen tiles {chosen} (each constant's best one-at-a-time variation)",
+             f"{len(times)} builds timed"]
+    write_tiles(TILE_TABLE, chosen, "\n".join("//   " + ln for ln in lines))
     print("wrote", TILE_TABLE, flush=True)
     if report:
         with open(report, "w") as f:
-            f.write("# Tile autotune\n\nCommand: `python -m paper_1311_5334_amd.autotune "
-                    f"--tiles --report {report}`\n\nSpace: {TILE_SPACE}. Workloads: c2 view 0 "
-                    "alone, c5 views 0-7 in one call, c3 views 0-15 in one call (device-resident); "
-                    "time: median device time of the whole path per call, 3 calls after 2 "
-                    "warm-up calls, each candidate built as a library of its own. Coordinate "
-                    "descent on the mean of the three times relative to the starting tiles.\n\n")
+            f.write("# Tile autotune\n\nCommands: `python -m paper_1311_5334_amd.autotune "
+                    "--build-tiles DIR` (CPU), then `python -m paper_1311_5334_amd.autotune "
+                    f"--tiles --prebuilt DIR --report {report}` (GPU)\n\nSpace: {TILE_SPACE}. "
+                    "Workloads: c2 view 0 alone, c5 views 0-7 in one call, c3 views 0-15 in one "
+                    "call (device-resident); time: median device time of the whole path per "
+                    "call, 3 calls after 2 warm-up calls, each candidate a library of its own. "
+                    "One-at-a-time variations of the starting tiles; each constant takes its "
+                    "best variation (by the mean time ratio to the start, if better by 1 %).\n\n")
             for ln in lines:
                 f.write(f"- {ln}\n")
-            f.write("\n| tiles | " + " | ".join(WORKLOADS) + " |\n|---|" +
-                    "---:|" * len(WORKLOADS) + "\n")
-            for key, res in cache.items():
-                f.write(f"| {dict(key)} | " + " | ".join(f"{res[w]:.3f}" for w in WORKLOADS) +
-                        " |\n")
+            f.write("\n| tiles | " + " | ".join(WORKLOADS) + " | ratio |\n|---|" +
+                    "---:|" * (len(WORKLOADS) + 1) + "\n")
+            for tiles, res in times:
+                f.write(f"| {tiles} | " + " | ".join(f"{res[w]:.3f}" for w in WORKLOADS) +
+                        f" | {score(res):.3f} |\n")
     return 0
 
 
@@ -256,8 +283,12 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     mode = ap.add_mutually_exclusive_group()
     mode.add_argument("--cells", action="store_true", help="tune the cell table (default)")
-    mode.add_argument("--tiles", action="store_true", help="tune the counting kernel's tiles")
+    mode.add_argument("--tiles", action="store_true",
+                      help="time prebuilt tile candidates (--prebuilt) and write the tile table")
+    mode.add_argument("--build-tiles", metavar="DIR",
+                      help="build the tile candidates into DIR (no GPU needed)")
     mode.add_argument("--time-lib", nargs=2, metavar=("LIB", "VIEWS"), help=argparse.SUPPRESS)
+    ap.add_argument("--prebuilt", metavar="DIR", help="directory written by --build-tiles")
     ap.add_argument("--table", default=TABLE)
     ap.add_argument("--report", default=None, help="also write a markdown summary here")
     args = ap.parse_args()
@@ -265,8 +296,12 @@ def main() -> int:
     if args.time_lib:
         print(json.dumps(time_library(*args.time_lib)), flush=True)
         return 0
+    if args.build_tiles:
+        return build_tiles(args.build_tiles)
     if args.tiles:
-        return tune_tiles(args.report)
+        if not args.prebuilt:
+            ap.error("--tiles needs --prebuilt DIR (made by --build-tiles)")
+        return tune_tiles(args.prebuilt, args.report)
     import torch
     from paper_1311_5334_amd import emt, synth
 

@@ -262,7 +262,7 @@ size_t cell_bytes(size_t n) {
     return 2 * bytes_of<uint32_t>(n) + bytes_of<uint32_t>(scan_scratch_words((uint32_t)n));
 }
 size_t view_bytes(size_t n) {
-    return bytes_of<ViewGrid>(n) + bytes_of<unsigned long long>(n) + 4 * bytes_of<uint32_t>(n + 1) +
+    return bytes_of<ViewGrid>(n) + bytes_of<unsigned long long>(n) + 5 * bytes_of<uint32_t>(n + 1) +
            bytes_of<Counters>(1) + bytes_of<uint32_t>((size_t)max_merge_rounds()) +
            bytes_of<uint32_t>(kGrabWords) + bytes_of<BatchDesc>(1);
 }
@@ -363,6 +363,7 @@ int ensure(emt_ctx *ctx, Caps &c) {
         d.view_ntr = carve<uint32_t>(p, n + 1);
         d.view_tr_off = carve<uint32_t>(p, n + 1);
         d.view_cursor = carve<uint32_t>(p, n + 1);
+        d.view_tail = carve<uint32_t>(p, n + 1);
         d.cnt = carve<Counters>(p, 1);
         d.undecided = carve<uint32_t>(p, (size_t)max_merge_rounds());
         d.grab = carve<uint32_t>(p, kGrabWords);

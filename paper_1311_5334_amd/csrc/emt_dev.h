@@ -166,6 +166,7 @@ struct DevPtrs {
     uint32_t *view_ntr;   // V
     uint32_t *view_tr_off;  // V + 1
     uint32_t *view_cursor;  // V
+    uint32_t *view_tail;    // V: candidates of each view handed to its merge tail
     uint32_t *scan_part;  // scan scratch
     Counters *cnt;
     const BatchDesc *desc;

@@ -175,8 +175,9 @@ void scan_excl(const uint32_t *in, const uint32_t *n_dev, uint32_t n_cap, uint32
 
 __global__ void __launch_bounds__(kBlock) k_zero(Counters *cnt, unsigned long long *view_seeds,
                                                  uint32_t *view_cand, uint32_t *view_ntr,
-                                                 uint32_t *view_cursor, uint32_t *cell_count,
-                                                 uint32_t *grab, const BatchDesc *desc) {
+                                                 uint32_t *view_cursor, uint32_t *view_tail,
+                                                 uint32_t *cell_count, uint32_t *grab,
+                                                 const BatchDesc *desc) {
     const uint32_t tid = grid_tid();
     const uint32_t n_views = desc->n_views, n_cells = desc->n_cells;
     if (tid == 0) {
@@ -189,6 +190,7 @@ __global__ void __launch_bounds__(kBlock) k_zero(Counters *cnt, unsigned long lo
         view_cand[v] = 0;
         view_ntr[v] = 0;
         view_cursor[v] = 0;
+        view_tail[v] = 0;
     }
     for (uint32_t i = tid; i < n_cells; i += grid_threads()) cell_count[i] = 0;
 }
@@ -990,7 +992,9 @@ constexpr int kCountRunCap = EMT_COUNT_RUN_CAP;     // queued runs per wave
 constexpr int kPieceWords = kPieceCap / 64;
 constexpr int kChunkSeeds = EMT_CHUNK_SEEDS;
 constexpr int kFetch = EMT_COUNT_FETCH;  // pencils a lane fetches per step
+constexpr int kRefillMin = EMT_COUNT_REFILL;  // waiting lanes that start a refill
 static_assert(64 * kFetch <= kCountRunCap, "a step's runs must fit the run queue");
+static_assert(kRefillMin >= 1 && kRefillMin <= 64, "refill threshold is a lane count");
 static_assert(64 * kLanePieces <= kPieceCap, "a step's pieces must fit the queue");
 static_assert(kPieceWords <= 64 && kPieceCap % 64 == 0, "one mask word per lane");
 static_assert(kPieceCap <= 4096 && kPiece * kLanePieces < 8192, "run record fields");
@@ -1173,11 +1177,17 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
                     more = chunk + nwv * kChunkSeeds < n_items;
                 }
             }
-            // take the next seeds into free slots
+            // take the next seeds into free slots. Setting up a seed (its
+            // loads, line constants and walk) runs with whatever lanes take
+            // one, so it is done in bulk: only once kRefillMin lanes wait, or
+            // when no lane is walking. A lane may idle a few steps; the
+            // set-up runs once per many seeds instead of almost every step.
             const bool want = !have && !(pend0 && pend1);
             const unsigned long long wm = __ballot(want);
+            const uint32_t n_want = (uint32_t)__popcll(wm);
+            const bool refill = n_want >= (uint32_t)kRefillMin || __ballot(have) == 0;
             const uint32_t rank = (uint32_t)__popcll(wm & lanes_below());
-            const bool take = want && next + rank < end;
+            const bool take = refill && want && next + rank < end;
             if (take) {
                 const uint32_t idx = next + rank;
                 cur = pend0 ? lane + 64 : lane;
@@ -1203,7 +1213,7 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
                 W.init(&d.grids[v], gi, dx, dy, dz, P.r, true, 0, 1, kFinite ? P.cyl_ext : -1);
                 have = true;
             }
-            next = min(end, next + (uint32_t)__popcll(wm));
+            if (refill) next = min(end, next + n_want);
             // fetch kFetch runs once the previous ones are queued
             bool drained = true;
 #pragma unroll
@@ -1488,24 +1498,52 @@ __global__ void __launch_bounds__(kBlock) k_round(DevPtrs d, Params P, int round
     if (kPhase == 1) flush_list(s_buf, &s_cnt, &s_base, &d.undecided[round], next);
 }
 
-// The remaining rounds in one workgroup, looping until no candidate is
-// undecided (each round decides at least the highest-priority one, so it
-// ends within as many rounds as there are candidates). Groups of eight lanes
-// take candidates of the list; __syncthreads separates the phases, and the
-// prune phase clears the reservations of the candidates' unused grains.
+// First candidate of view v: candidates are listed in seed order, and a
+// view's seeds are contiguous.
+__device__ __forceinline__ uint32_t view_first_cand(const DevPtrs &d, uint32_t v, uint32_t ns) {
+    return d.cand_pos[min(d.seed_off[d.grids[v].grain_off], ns)];
+}
+
+// Candidates of different views share no grain, so the rounds the grid-wide
+// kernels leave are finished view by view, one workgroup each. First the
+// undecided list is split by view: view v's go to its own stretch of the
+// other list, starting at its first candidate (a view never has more
+// undecided candidates than candidates). The order within a stretch does not
+// matter: outcomes depend only on the keys.
+__global__ void __launch_bounds__(kBlock) k_tail_split(DevPtrs d, int last_round) {
+    const uint32_t n = d.undecided[last_round];
+    const uint32_t *list = merge_list(d, last_round + 1);
+    uint32_t *out = merge_list(d, last_round + 2);
+    const uint32_t ns = d.cnt->n_seeds_ok;
+    for (uint32_t i = grid_tid(); i < n; i += grid_threads()) {
+        const uint32_t ci = list[i];
+        const uint32_t v = d.cand[ci].v;
+        out[view_first_cand(d, v, ns) + atomicAdd(&d.view_tail[v], 1u)] = ci;
+    }
+}
+
+// The remaining rounds of one view in one workgroup, looping until none of
+// its candidates is undecided (each round decides at least the highest-
+// priority one, so it ends within as many rounds as there are candidates).
+// Groups of eight lanes take candidates of the list; __syncthreads separates
+// the phases, and the prune phase clears the reservations of the
+// candidates' unused grains.
 constexpr int kTailBlock = 1024;
 
 __global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, int last_round) {
+    const uint32_t view = blockIdx.x;
+    if (view >= d.desc->n_views) return;
     __shared__ uint32_t s_n[2];
     const int sub = threadIdx.x & (kMergeGroup - 1);
     const uint32_t group = threadIdx.x / kMergeGroup;
     constexpr uint32_t kTailGroups = kTailBlock / kMergeGroup;
+    const uint32_t c0 = view_first_cand(d, view, d.cnt->n_seeds_ok);
     if (threadIdx.x == 0) {
-        s_n[0] = d.undecided[last_round];
+        s_n[0] = d.view_tail[view];
         s_n[1] = 0;
     }
     __syncthreads();
-    uint32_t *list[2] = {merge_list(d, last_round + 1), merge_list(d, last_round + 2)};
+    uint32_t *list[2] = {merge_list(d, last_round + 2) + c0, merge_list(d, last_round + 3) + c0};
     int cur = 0;
     uint32_t rounds = 0;
     const uint32_t limit = s_n[0] + 2;
@@ -1589,8 +1627,8 @@ __global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, 
         // grid-wide rounds that ran: round r runs while round r-1 left some
         uint32_t wide = d.cnt->n_act[0] ? 1u : 0u;
         while (wide >= 1 && wide <= (uint32_t)last_round && d.undecided[wide - 1]) ++wide;
-        d.cnt->rounds = wide + rounds;
-        if (s_n[cur] > 0) d.cnt->err |= 4u;
+        atomicMax(&d.cnt->rounds, wide + rounds);
+        if (s_n[cur] > 0) atomicOr(&d.cnt->err, 4u);
     }
 }
 
@@ -2320,8 +2358,8 @@ size_t scan_scratch_words(uint32_t n_cap) { return (size_t)n_cap / kScanTile + 2
 
 void launch_prepare(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {
     k_zero<<<blocks_for(c.n_cells, 1024), kBlock, 0, s>>>(d.cnt, d.view_seeds, d.view_cand,
-                                                          d.view_ntr, d.view_cursor, d.cell_count,
-                                                          d.grab, d.desc);
+                                                          d.view_ntr, d.view_cursor, d.view_tail,
+                                                          d.cell_count, d.grab, d.desc);
 }
 
 void launch_bin(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
@@ -2389,7 +2427,8 @@ void launch_merge(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t 
         k_round<1><<<nb, kBlock, 0, s>>>(d, P, round);
         if (round >= 1 && nb > 1024) nb = nb / 2 > 1024 ? nb / 2 : 1024;
     }
-    k_merge_tail<<<1, kTailBlock, 0, s>>>(d, P, wide - 1);
+    k_tail_split<<<64, kBlock, 0, s>>>(d, wide - 1);
+    k_merge_tail<<<c.n_views, kTailBlock, 0, s>>>(d, P, wide - 1);
 }
 
 int max_merge_rounds() { return kMaxRounds; }

@@ -15,6 +15,9 @@
 #ifndef EMT_COUNT_FETCH
 #define EMT_COUNT_FETCH 4  // cell pencils a lane fetches per step
 #endif
+#ifndef EMT_COUNT_REFILL
+#define EMT_COUNT_REFILL 32  // lanes waiting for a seed before a wave refills
+#endif
 #ifndef EMT_CHUNK_SEEDS
 #define EMT_CHUNK_SEEDS 128  // seeds a wave takes at a time (single views)
 #endif
