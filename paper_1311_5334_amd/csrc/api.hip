@@ -264,7 +264,8 @@ size_t cell_bytes(size_t n) {
 size_t view_bytes(size_t n) {
     return bytes_of<ViewGrid>(n) + bytes_of<unsigned long long>(n) + 5 * bytes_of<uint32_t>(n + 1) +
            bytes_of<Counters>(1) + bytes_of<uint32_t>((size_t)max_merge_rounds()) +
-           bytes_of<uint32_t>(kGrabWords) + bytes_of<BatchDesc>(1);
+           bytes_of<uint32_t>(kGrabWords) + bytes_of<unsigned long long>(kPartWords) +
+           bytes_of<BatchDesc>(1);
 }
 // the scan scratch serves every scan: cells, anchors, seeds, candidates
 uint32_t scan_words(const Caps &c) {
@@ -367,6 +368,7 @@ int ensure(emt_ctx *ctx, Caps &c) {
         d.cnt = carve<Counters>(p, 1);
         d.undecided = carve<uint32_t>(p, (size_t)max_merge_rounds());
         d.grab = carve<uint32_t>(p, kGrabWords);
+        d.part64 = carve<unsigned long long>(p, kPartWords);
         d.desc = carve<BatchDesc>(p, 1);
         ctx->cap_views = (uint32_t)n;
         // matching pinned staging of the view table

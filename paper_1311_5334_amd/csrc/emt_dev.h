@@ -53,6 +53,13 @@ struct BatchDesc {
 // Per-XCD seed-range counters of the counting kernel, 64 B apart.
 constexpr int kGrabWords = 8 * 16;
 constexpr int kCellBuckets = 8;
+// Partial sums of four 64-bit totals (seeds, member entries, counting tests,
+// counting hits): kPartSlots counters per total, one 128-byte line apart, so
+// that the workgroups' atomic adds spread over many L2 addresses instead of
+// serialising on one.
+constexpr int kPartSlots = 64;
+constexpr int kPartStride = 16;
+constexpr int kPartWords = 4 * kPartSlots * kPartStride;
 constexpr double kCellEdge0 = 0.75;
 
 struct Params {
@@ -167,6 +174,7 @@ struct DevPtrs {
     uint32_t *view_tr_off;  // V + 1
     uint32_t *view_cursor;  // V
     uint32_t *view_tail;    // V: candidates of each view handed to its merge tail
+    unsigned long long *part64;  // kPartWords: spread partial sums of four 64-bit totals
     uint32_t *scan_part;  // scan scratch
     Counters *cnt;
     const BatchDesc *desc;

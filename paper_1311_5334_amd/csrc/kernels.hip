@@ -66,6 +66,25 @@ __device__ __forceinline__ void wave_sync_mem() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Adds a workgroup's total of wave-uniform values v (one per wave) to one
+// of the kPartSlots counters of total `which`: the waves' values are summed
+// in LDS, then one atomic per workgroup, the workgroups spread over the
+// counters. Every thread of the workgroup must call it (it synchronises the
+// workgroup twice).
+__device__ __forceinline__ void add_spread(unsigned long long *part64, int which,
+                                           unsigned long long v) {
+    __shared__ unsigned long long s_part[kBlock / 64];
+    if (lane_id() == 0) s_part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (uint32_t w = 0; w < blockDim.x / 64; ++w) t += s_part[w];
+        if (t)
+            atomicAdd(&part64[(which * kPartSlots + (int)(blockIdx.x % kPartSlots)) * kPartStride], t);
+    }
+    __syncthreads();  // s_part is free again for the next call
+}
+
 __device__ __forceinline__ uint32_t grid_tid() { return blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ uint32_t grid_threads() { return gridDim.x * blockDim.x; }
 
@@ -177,6 +196,7 @@ __global__ void __launch_bounds__(kBlock) k_zero(Counters *cnt, unsigned long lo
                                                  uint32_t *view_cand, uint32_t *view_ntr,
                                                  uint32_t *view_cursor, uint32_t *view_tail,
                                                  uint32_t *cell_count, uint32_t *grab,
+                                                 unsigned long long *part64,
                                                  const BatchDesc *desc) {
     const uint32_t tid = grid_tid();
     const uint32_t n_views = desc->n_views, n_cells = desc->n_cells;
@@ -185,6 +205,7 @@ __global__ void __launch_bounds__(kBlock) k_zero(Counters *cnt, unsigned long lo
         *cnt = z;
     }
     if (tid < kGrabWords) grab[tid] = 0;
+    for (uint32_t i = tid; i < (uint32_t)kPartWords; i += grid_threads()) part64[i] = 0;
     for (uint32_t v = tid; v < n_views; v += grid_threads()) {
         view_seeds[v] = 0;
         view_cand[v] = 0;
@@ -730,16 +751,19 @@ __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
             wave_total += mine;
         }
     }
-    if (!kWrite && lane == 0 && wave_total) atomicAdd(&d.cnt->seeds64, wave_total);
+    if constexpr (!kWrite) add_spread(d.part64, 0, wave_total);
 }
 
 // The seed total of the uint32 scan, replaced by the exact 64-bit count
 // (saturated to 2^32 - 1), and the number of seeds the later stages take:
 // none when they do not fit the seed buffer (the host then re-runs the call
 // with a larger one, or fails if no buffer can hold them).
-__global__ void k_seed_total(Counters *cnt, unsigned long long seed_cap) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    const unsigned long long s = cnt->seeds64;
+__global__ void k_seed_total(Counters *cnt, const unsigned long long *part64,
+                             unsigned long long seed_cap) {
+    // one wave: the spread partial sums (kPartSlots == 64, one per lane)
+    const unsigned long long s = wave_sum(part64[lane_id() * kPartStride]);
+    if (threadIdx.x != 0) return;
+    cnt->seeds64 = s;
     const uint32_t n = s > 0xffffffffull ? 0xffffffffu : (uint32_t)s;
     cnt->n_seeds = n;
     cnt->n_seeds_ok = n <= seed_cap ? n : 0u;
@@ -747,9 +771,15 @@ __global__ void k_seed_total(Counters *cnt, unsigned long long seed_cap) {
 
 // Likewise for the member entries (the scan of candidate counts): a total
 // that wrapped reads as an overflow, so no stage uses the wrapped offsets.
-__global__ void k_member_total(Counters *cnt) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    const unsigned long long m = cnt->members64;
+__global__ void k_member_total(Counters *cnt, const unsigned long long *part64) {
+    const unsigned long long m = wave_sum(part64[(kPartSlots + lane_id()) * kPartStride]);
+    // the counting kernel's tests and hits, summed here (it has finished)
+    const unsigned long long t = wave_sum(part64[(2 * kPartSlots + lane_id()) * kPartStride]);
+    const unsigned long long h = wave_sum(part64[(3 * kPartSlots + lane_id()) * kPartStride]);
+    if (threadIdx.x != 0) return;
+    cnt->tests = t;
+    cnt->hits = h;
+    cnt->members64 = m;
     cnt->n_members = m > 0xffffffffull ? 0xffffffffu : (uint32_t)m;
 }
 
@@ -1284,12 +1314,8 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
             }
         }
     }
-    tests = wave_sum(tests);
-    hits = wave_sum(hits);
-    if (lane == 0) {
-        atomicAdd(&d.cnt->tests, tests);
-        atomicAdd(&d.cnt->hits, hits);
-    }
+    add_spread(d.part64, 2, wave_sum(tests));
+    add_spread(d.part64, 3, wave_sum(hits));
 }
 
 // Candidates in seed order: position from the flag scan of seed_n; their
@@ -1323,8 +1349,7 @@ __global__ void __launch_bounds__(kBlock) k_cand_scatter(DevPtrs d, Caps c, Para
         if (P.thr_num) d.cand_thr[pos] = seed_threshold(gj.x - gi.x, gj.y - gi.y, gj.z - gi.z, P);
         d.key[pos] = cand_key(n, (uint32_t)gi.w, (uint32_t)gj.w);
     }
-    listed = wave_sum(listed);
-    if (lane_id() == 0 && listed) atomicAdd(&d.cnt->members64, listed);
+    add_spread(d.part64, 1, wave_sum(listed));
 }
 
 // The threshold a candidate's unused grains must reach: n_min, or its own
@@ -1634,15 +1659,46 @@ __global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, 
 
 // ------------------------------------------------------------------- fit
 
+// Accepted candidates into the list of tracks (any order: tracks are ranked
+// by key afterwards) and the track count of each view. A workgroup counts its
+// accepted candidates first and reserves their slots with one atomic; a
+// wave adds to a view's count once for its lanes of that view (a wave's
+// candidates are consecutive, so nearly always of one view).
 __global__ void __launch_bounds__(kBlock) k_collect(DevPtrs d, Caps c) {
+    __shared__ uint32_t s_cnt, s_base;
     const Counters *cn = d.cnt;
     const uint32_t nc = cn->err ? 0u : min(cn->n_cand, c.cand_cap);
-    for (uint32_t i = grid_tid(); i < nc; i += grid_threads()) {
-        if (d.status[i] == kAccepted) {
-            const uint32_t slot = atomicAdd(&d.cnt->n_acc, 1u);
-            d.acc[slot] = i;
-            atomicAdd(&d.view_ntr[d.cand[i].v], 1u);
+    const int lane = lane_id();
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    for (uint32_t b = blockIdx.x * blockDim.x; b < nc; b += grid_threads()) {
+        const uint32_t i = b + threadIdx.x;
+        const unsigned long long m = __ballot(i < nc && d.status[i] == kAccepted);
+        if (lane == 0 && m) atomicAdd(&s_cnt, (uint32_t)__popcll(m));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_base = s_cnt ? atomicAdd(&d.cnt->n_acc, s_cnt) : 0u;
+        s_cnt = 0;
+    }
+    __syncthreads();
+    for (uint32_t b = blockIdx.x * blockDim.x; b < nc; b += grid_threads()) {
+        const uint32_t i = b + threadIdx.x;
+        const bool a = i < nc && d.status[i] == kAccepted;
+        const unsigned long long m = __ballot(a);
+        if (!m) continue;
+        uint32_t w = 0;
+        if (lane == 0) w = atomicAdd(&s_cnt, (uint32_t)__popcll(m));
+        w = (uint32_t)__shfl((int)w, 0);
+        const uint32_t v = a ? d.cand[i].v : 0u;
+        const int first = __ffsll((long long)m) - 1;
+        const uint32_t v0 = (uint32_t)__shfl((int)v, first);
+        if (a) {
+            d.acc[s_base + w + (uint32_t)__popcll(m & lanes_below())] = i;
+            if (v != v0) atomicAdd(&d.view_ntr[v], 1u);
         }
+        const uint32_t same = (uint32_t)__popcll(__ballot(a && v == v0));
+        if (lane == first) atomicAdd(&d.view_ntr[v0], same);
     }
 }
 
@@ -2359,7 +2415,7 @@ size_t scan_scratch_words(uint32_t n_cap) { return (size_t)n_cap / kScanTile + 2
 void launch_prepare(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {
     k_zero<<<blocks_for(c.n_cells, 1024), kBlock, 0, s>>>(d.cnt, d.view_seeds, d.view_cand,
                                                           d.view_ntr, d.view_cursor, d.view_tail,
-                                                          d.cell_count, d.grab, d.desc);
+                                                          d.cell_count, d.grab, d.part64, d.desc);
 }
 
 void launch_bin(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
@@ -2379,7 +2435,7 @@ void launch_seeds(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t 
     // the scan total counts every seed (it wraps only above 2^32 - 1 a call)
     // offsets in uint32: exact whenever the total fits, which k_seed_total checks
     scan_excl(d.seed_cnt, &d.desc->n_total, c.n_total, d.scan_part, d.seed_off, &d.cnt->n_seeds, s);
-    k_seed_total<<<1, 64, 0, s>>>(d.cnt, c.seed_cap);
+    k_seed_total<<<1, 64, 0, s>>>(d.cnt, d.part64, c.seed_cap);
     k_seeds<true><<<nb, kBlock, 0, s>>>(d, c, P);
 }
 
@@ -2398,7 +2454,7 @@ void launch_candidates(const DevPtrs &d, const Caps &c, const Params &P, hipStre
 
 void launch_members(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
     scan_excl(d.cand_n, &d.cnt->n_cand, c.cand_cap, d.scan_part, d.mem_off, &d.cnt->n_members, s);
-    k_member_total<<<1, 64, 0, s>>>(d.cnt);
+    k_member_total<<<1, 64, 0, s>>>(d.cnt, d.part64);
     const uint32_t nb =
         blocks_for((unsigned long long)EMT_MEMBER_LANES * c.cand_cap, kPersistentBlocks);
     if (P.cyl_ext >= 0)
