@@ -929,7 +929,8 @@ int finish_views(emt_ctx *ctx, emt_view_out *out) {
         ctx->cand_off[n_views] = o;
         ctx->last_views = n_views;
     }
-    ctx->next_wide = std::max(6, std::min(max_wide_rounds(), (int)h.rounds + 2));
+    ctx->next_wide = std::max(std::min(6, max_wide_rounds()),
+                              std::min(max_wide_rounds(), (int)h.rounds + 2));
     emt_call_stats &st = ctx->last;
     st = emt_call_stats{};
     st.n_seeds = h.seeds64;

@@ -1378,6 +1378,9 @@ __device__ __forceinline__ uint32_t cand_min(const DevPtrs &d, const Params &P, 
 
 constexpr int kMaxRounds = 256;
 constexpr int kWideRounds = 16;  // most grid-wide rounds (distinct key tags) before the tail
+// rounds a call runs grid-wide at most before the per-view tails take over
+constexpr int kWideCap = EMT_MERGE_WIDE;
+static_assert(kWideCap >= 1 && kWideCap <= kWideRounds, "grid-wide merge rounds");
 
 __global__ void __launch_bounds__(kBlock) k_merge_init(DevPtrs d, Caps c) {
     const Counters *cn = d.cnt;
@@ -1410,6 +1413,15 @@ __global__ void __launch_bounds__(kBlock) k_merge_init(DevPtrs d, Caps c) {
 // down, so the keys of a newer round lie below every older value and no
 // clearing pass is needed between rounds (keys use 60 bits: n, i and j are
 // below 2^20 each).
+// A reservation: the owner word keeps the smallest key offered to it in a
+// round. It only decreases during a round, so a value read at or below key
+// means an equal or better reservation is already there and the atomic
+// would change nothing; most grains are offered to many candidates, and the
+// read spares most of the atomics.
+__device__ __forceinline__ void reserve(unsigned long long *owner, unsigned long long key) {
+    if (*owner > key) atomicMin(owner, key);
+}
+
 constexpr int kMergeGroup = 8;
 static_assert(kWideRounds <= 16, "round tags take four bits");
 
@@ -1469,16 +1481,20 @@ __global__ void __launch_bounds__(kBlock) k_round(DevPtrs d, Params P, int round
             const unsigned long long key = d.key[ci] | tag;
             const uint32_t e0 = d.mem_off[ci], e1 = e0 + d.cand[ci].n;
             if (kPhase == 0) {  // prune, then reserve
+                // round 0: no grain is used yet and every candidate reached
+                // its threshold, so nothing is pruned
                 uint32_t unused = 0;
-                for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup)
-                    unused += d.used[d.members[e]] ? 0u : 1u;
-                unused = group_sum8(unused);
-                if (unused < cand_min(d, P, ci)) {
+                if (round > 0) {
+                    for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup)
+                        unused += d.used[d.members[e]] ? 0u : 1u;
+                    unused = group_sum8(unused);
+                }
+                if (round > 0 && unused < cand_min(d, P, ci)) {
                     if (sub == 0) d.status[ci] = kRejected;
                 } else {
                     for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
                         const uint32_t k = d.members[e];
-                        if (!d.used[k]) atomicMin(&d.owner[k], key);
+                        if (round == 0 || !d.used[k]) reserve(&d.owner[k], key);
                     }
                 }
             } else {  // decide
@@ -1601,7 +1617,7 @@ __global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, 
             const uint32_t e0 = d.mem_off[ci], e1 = e0 + d.cand[ci].n;
             for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
                 const uint32_t k = d.members[e];
-                if (!d.used[k]) atomicMin(&d.owner[k], key);
+                if (!d.used[k]) reserve(&d.owner[k], key);
             }
         }
         __threadfence_block();
@@ -2488,7 +2504,7 @@ void launch_merge(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t 
 }
 
 int max_merge_rounds() { return kMaxRounds; }
-int max_wide_rounds() { return kWideRounds; }
+int max_wide_rounds() { return kWideCap; }
 
 void launch_copy_out(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {
     k_copy_out<<<64, kBlock, 0, s>>>(d, c);

@@ -24,6 +24,9 @@
 #ifndef EMT_COUNT_BLOCKS
 #define EMT_COUNT_BLOCKS 1024  // workgroups of the counting kernel
 #endif
+#ifndef EMT_MERGE_WIDE
+#define EMT_MERGE_WIDE 16  // grid-wide merge rounds at most before the per-view tails
+#endif
 #ifndef EMT_CELLS_PER_GRAIN
 #define EMT_CELLS_PER_GRAIN 4  // cells a view may use per grain (plus 4096)
 #endif
