@@ -100,6 +100,8 @@ TILE_SPACE = {
     "EMT_COUNT_REFILL": (16, 32, 48),
     "EMT_CHUNK_SEEDS": (64, 128, 256),
     "EMT_COUNT_BLOCKS": (1024, 2048),
+    "EMT_COUNT_OCCUPANCY": (4, 5),
+    "EMT_MERGE_WIDE": (12, 16),
     "EMT_CELLS_PER_GRAIN": (4, 8),
 }
 TILE_COMMENTS = {
@@ -109,6 +111,8 @@ TILE_COMMENTS = {
     "EMT_COUNT_REFILL": "lanes waiting for a seed before a wave refills",
     "EMT_CHUNK_SEEDS": "seeds a wave takes at a time (single views)",
     "EMT_COUNT_BLOCKS": "workgroups of the counting kernel",
+    "EMT_COUNT_OCCUPANCY": "waves per SIMD the counting kernel is compiled for",
+    "EMT_MERGE_WIDE": "grid-wide merge rounds at most before the per-view tails",
     "EMT_CELLS_PER_GRAIN": "cells a view may use per grain (plus 4096)",
 }
 WORKLOADS = ("c2", "c5x8", "c3x16")

@@ -1032,11 +1032,11 @@ static_assert(kPiece >= 1 && (uint32_t)kPiece - 1u <= kSortedSpare, "piece size"
 
 template <bool kFinite>
 struct CountLds {
-    // line constants per seed slot (floats): d, -d, -(g_i x d), the band
+    // line constants per seed slot (floats): d, -(g_i x d), the band
     // [tlo, thi] of the FP32 test, and the sorted position of g_i
     float4 la[kCountSlots];  // dx, dy, dz, tlo
-    float4 lb[kCountSlots];  // -dx, -dy, -dz, thi
     float4 lc[kCountSlots];  // -ex, -ey, -ez, (bits) sorted position of g_i
+    float lthi[kCountSlots];  // thi
     int2 pc[kFinite ? kCountSlots : 1];  // finite cylinder: bounds of g_k.d
     uint32_t cnt[kCountSlots];
     unsigned long long mask[kPieceWords];  // bit s: a run starts at piece s
@@ -1054,7 +1054,7 @@ struct CountLds {
 // |d|^2, both widened by 2^-20 for the rounding of the squares (tlo < 0
 // when r <= 1/8); in between the test is redone in int64.
 __device__ __forceinline__ void line_consts(int4 gi, int dx, int dy, int dz, int r, uint32_t p,
-                                            float4 &A, float4 &B, float4 &C) {
+                                            float4 &A, float &thi_out, float4 &C) {
     const long long D = (long long)dx * dx + (long long)dy * dy + (long long)dz * dz;
     const double sd = sqrt((double)D);
     const double lo = (double)r * sd - 0.125 * sd, hi = (double)r * sd + 0.125 * sd;
@@ -1064,7 +1064,7 @@ __device__ __forceinline__ void line_consts(int4 gi, int dx, int dy, int dz, int
     const long long ey = (long long)gi.z * dx - (long long)gi.x * dz;
     const long long ez = (long long)gi.x * dy - (long long)gi.y * dx;
     A = make_float4((float)dx, (float)dy, (float)dz, tlo);
-    B = make_float4((float)-dx, (float)-dy, (float)-dz, thi);
+    thi_out = thi;
     C = make_float4((float)-ex, (float)-ey, (float)-ez, __uint_as_float(p));
 }
 
@@ -1091,7 +1091,8 @@ __device__ __forceinline__ void count_flush(CountLds<kFinite> &Q, uint32_t qn, i
             const uint32_t sl = (rec.y >> 12) & 0x7fu;
             const uint32_t k0 = rec.x + (uint32_t)kPiece * q;
             const uint32_t m = min((rec.y >> 19) - (uint32_t)kPiece * q, (uint32_t)kPiece);
-            const float4 A = Q.la[sl], B = Q.lb[sl], C = Q.lc[sl];
+            const float4 A = Q.la[sl], C = Q.lc[sl];
+            const float thi = Q.lthi[sl];
             // the sorted grains carry kPiece - 1 spare entries past the
             // last one, so a piece's loads stay in bounds
             const float4 *pp = sgf + k0;
@@ -1101,9 +1102,9 @@ __device__ __forceinline__ void count_flush(CountLds<kFinite> &Q, uint32_t qn, i
             uint32_t n = 0, amb = 0;
 #pragma unroll
             for (int t = 0; t < kPiece; ++t) {
-                const float c0 = fmaf(h[t].y, A.z, fmaf(h[t].z, B.y, C.x));
-                const float c1 = fmaf(h[t].z, A.x, fmaf(h[t].x, B.z, C.y));
-                const float c2 = fmaf(h[t].x, A.y, fmaf(h[t].y, B.x, C.z));
+                const float c0 = fmaf(h[t].y, A.z, fmaf(h[t].z, -A.y, C.x));
+                const float c1 = fmaf(h[t].z, A.x, fmaf(h[t].x, -A.z, C.y));
+                const float c2 = fmaf(h[t].x, A.y, fmaf(h[t].y, -A.x, C.z));
                 const float fc = fmaf(c0, c0, fmaf(c1, c1, c2 * c2));
                 bool ok = (uint32_t)t < m;
                 if constexpr (kFinite) {
@@ -1111,7 +1112,7 @@ __device__ __forceinline__ void count_flush(CountLds<kFinite> &Q, uint32_t qn, i
                     const int4 Ai = make_int4((int)A.x, (int)A.y, (int)A.z, 0);
                     ok = ok && axial_ok(hi, Ai, Q.pc[sl]);
                 }
-                const bool in_lo = fc <= A.w, in_hi = fc <= B.w;
+                const bool in_lo = fc <= A.w, in_hi = fc <= thi;
                 n += (ok && in_lo) ? 1u : 0u;
                 amb |= (ok && in_hi && !in_lo) ? (1u << t) : 0u;
             }
@@ -1140,8 +1141,14 @@ __device__ __forceinline__ void count_flush(CountLds<kFinite> &Q, uint32_t qn, i
     wave_lds_sync();
 }
 
+// Waves per SIMD the counting kernel is compiled for: its test phase waits
+// on grain loads, so more resident waves hide more of that latency (the
+// compiler then keeps the kernel within 512 / kCountOccupancy VGPRs).
+constexpr int kCountOccupancy = EMT_COUNT_OCCUPANCY;
+
 template <bool kFinite>
-__global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kCountOccupancy)))
+k_count(DevPtrs d, Caps c, Params P) {
     __shared__ CountLds<kFinite> sQ[kWaves];
     const int lane = lane_id();
     CountLds<kFinite> &Q = sQ[threadIdx.x >> 6];
@@ -1234,11 +1241,12 @@ __global__ void __launch_bounds__(kBlock) k_count(DevPtrs d, Caps c, Params P) {
                     th1 = th;
                 }
                 if constexpr (kFinite) Q.pc[cur] = axial_bounds(gi, dx, dy, dz, P.cyl_ext);
-                float4 A, B, C;
-                line_consts(gi, dx, dy, dz, P.r, pq.x, A, B, C);
+                float4 A, C;
+                float thi;
+                line_consts(gi, dx, dy, dz, P.r, pq.x, A, thi, C);
                 Q.la[cur] = A;
-                Q.lb[cur] = B;
                 Q.lc[cur] = C;
+                Q.lthi[cur] = thi;
                 Q.cnt[cur] = 0;
                 W.init(&d.grids[v], gi, dx, dy, dz, P.r, true, 0, 1, kFinite ? P.cyl_ext : -1);
                 have = true;

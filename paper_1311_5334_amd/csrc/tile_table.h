@@ -27,6 +27,9 @@
 #ifndef EMT_MERGE_WIDE
 #define EMT_MERGE_WIDE 16  // grid-wide merge rounds at most before the per-view tails
 #endif
+#ifndef EMT_COUNT_OCCUPANCY
+#define EMT_COUNT_OCCUPANCY 4  // waves per SIMD the counting kernel is compiled for
+#endif
 #ifndef EMT_CELLS_PER_GRAIN
 #define EMT_CELLS_PER_GRAIN 4  // cells a view may use per grain (plus 4096)
 #endif
