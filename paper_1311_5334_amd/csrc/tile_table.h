@@ -2,7 +2,9 @@
 // the cell budget per grain, chosen by paper_1311_5334_amd/autotune.py
 // --tiles from timings of the whole path; -D on the compiler line overrides
 // each value.
-//   (hand-set starting values; not yet tuned)
+//   starting tiles {'EMT_COUNT_PIECE': 4, 'EMT_COUNT_LANE_PIECES': 8, 'EMT_COUNT_FETCH': 4, 'EMT_COUNT_REFILL': 32, 'EMT_CHUNK_SEEDS': 128, 'EMT_COUNT_BLOCKS': 1024, 'EMT_COUNT_OCCUPANCY': 4, 'EMT_MERGE_WIDE': 16, 'EMT_CELLS_PER_GRAIN': 4}: c2 1.190 ms, c5x8 45.040 ms, c3x16 6.319 ms
+//   chosen tiles {'EMT_COUNT_PIECE': 4, 'EMT_COUNT_LANE_PIECES': 16, 'EMT_COUNT_FETCH': 4, 'EMT_COUNT_REFILL': 32, 'EMT_CHUNK_SEEDS': 128, 'EMT_COUNT_BLOCKS': 1024, 'EMT_COUNT_OCCUPANCY': 4, 'EMT_MERGE_WIDE': 16, 'EMT_CELLS_PER_GRAIN': 4} (each constant's best one-at-a-time variation)
+//   14 builds timed
 #ifndef EMT_TILE_TABLE_H
 #define EMT_TILE_TABLE_H
 
@@ -10,7 +12,7 @@
 #define EMT_COUNT_PIECE 4  // grains a flush lane tests per queue entry
 #endif
 #ifndef EMT_COUNT_LANE_PIECES
-#define EMT_COUNT_LANE_PIECES 8  // queue entries a lane adds per step
+#define EMT_COUNT_LANE_PIECES 16  // queue entries a lane adds per step
 #endif
 #ifndef EMT_COUNT_FETCH
 #define EMT_COUNT_FETCH 4  // cell pencils a lane fetches per step
@@ -24,11 +26,11 @@
 #ifndef EMT_COUNT_BLOCKS
 #define EMT_COUNT_BLOCKS 1024  // workgroups of the counting kernel
 #endif
-#ifndef EMT_MERGE_WIDE
-#define EMT_MERGE_WIDE 16  // grid-wide merge rounds at most before the per-view tails
-#endif
 #ifndef EMT_COUNT_OCCUPANCY
 #define EMT_COUNT_OCCUPANCY 4  // waves per SIMD the counting kernel is compiled for
+#endif
+#ifndef EMT_MERGE_WIDE
+#define EMT_MERGE_WIDE 16  // grid-wide merge rounds at most before the per-view tails
 #endif
 #ifndef EMT_CELLS_PER_GRAIN
 #define EMT_CELLS_PER_GRAIN 4  // cells a view may use per grain (plus 4096)
