@@ -36,9 +36,9 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # multiplies, 2 adds), one compare.
 OPS_PER_TEST = 18
 HBM_PEAK_GBS = 8000.0
-# the counting kernel's code and the cell table that shapes its work
+# the counting kernel's code and the tables that shape its work
 COUNT_KERNEL_SRCS = [os.path.join(ROOT, "paper_1311_5334_amd", "csrc", f)
-                     for f in ("kernels.hip", "cell_table.h")]
+                     for f in ("kernels.hip", "cell_table.h", "tile_table.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "count_traffic.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "count_valu.json")
 BIN_BYTES_PER_GRAIN = 44
@@ -85,7 +85,10 @@ def valu_counters_for_current_kernel():
         return None
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return {k: rec[k] for k in ("valu_issue_frac", "lane_util", "lane_ops_frac_of_peak")}
+    keys = ("workload", "valu_issue_frac", "lane_util", "lane_ops_frac_of_peak",
+            "valu_lane_ops_per_test", "lds_active_frac", "lds_bank_conflict_frac",
+            "lds_insts_per_test", "lds_bytes_per_s_frac_of_measured")
+    return {k: rec[k] for k in keys if k in rec}
 
 
 def _lscpu() -> dict:
@@ -259,6 +262,23 @@ def measure_served(emt, views, n_req: int, warmup: int, batch: int = 16,
             for k in range(0, len(xyzs), batch):
                 tr(xyzs[k:k + batch])
         mu_b = reps * len(xyzs) / (time.perf_counter() - t0)
+    # the counting kernel on the same batches the server forms at load,
+    # timed stage by stage (a separate pass, so mu_b is not slowed by events)
+    tests, count_s = 0, 0.0
+    with emt.Tracker(device=0, flags=emt.EMT_F_STATS) as tr:
+        for k in range(0, len(xyzs), batch):
+            tr(xyzs[k:k + batch])
+            st = tr.stats()
+            tests += st["n_tests"]
+            count_s += st["ms"]["count"] * 1e-3
+    if count_s > 0:
+        ach = tests * OPS_PER_TEST / count_s / 1e12
+        out["count_roofline"] = {"achieved": round(ach, 3), "unit": "Tops/s",
+                                 "peak": round(VALU_PEAK_OPS / 1e12, 2),
+                                 "frac": round(ach / (VALU_PEAK_OPS / 1e12), 4),
+                                 "note": "k_count over the pool in batches of the served "
+                                         "size, 18 ops per (seed, grain) test"}
+    with emt.Tracker(device=0) as tr:
         lat = []
         t0 = time.perf_counter()
         for x in xyzs:

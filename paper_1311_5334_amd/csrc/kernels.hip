@@ -730,8 +730,12 @@ __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
                                 (unsigned long long)base + (unsigned long long)__popcll(m & lanes_below());
                             // stored lower input index first: that grain is
                             // the seed's i (the fit's origin and key order)
-                            if (slot < c.seed_cap)
+                            if (slot < c.seed_cap) {
                                 d.seeds[slot] = h.w > g.w ? make_uint2(p, q) : make_uint2(q, p);
+                                // counts below the threshold stay 0: the
+                                // counting kernel writes only the others
+                                d.seed_n[slot] = 0u;
+                            }
                         }
                         base += (uint32_t)__popcll(m);
                     } else {
@@ -1186,16 +1190,19 @@ k_count(DevPtrs d, Caps c, Params P) {
     uint32_t qn = 0, nr = 0;
     // counts of closed slots are final after a flush: write them, free slots
     auto finalize = [&]() {
+        // seed_n is 0 from the seed pass; only counts that reach the
+        // threshold are written (a few percent: scattered 4-byte stores of
+        // every count would each cost a partial line write)
         if (pend0) {
             const uint32_t n = Q.cnt[lane];
             hits += n;
-            d.seed_n[idx0] = n >= th0 ? n : 0u;
+            if (n >= th0) d.seed_n[idx0] = n;
             pend0 = false;
         }
         if (pend1) {
             const uint32_t n = Q.cnt[lane + 64];
             hits += n;
-            d.seed_n[idx1] = n >= th1 ? n : 0u;
+            if (n >= th1) d.seed_n[idx1] = n;
             pend1 = false;
         }
         wave_lds_sync();
