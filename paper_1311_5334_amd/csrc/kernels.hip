@@ -1027,6 +1027,8 @@ constexpr int kPieceWords = kPieceCap / 64;
 constexpr int kChunkSeeds = EMT_CHUNK_SEEDS;
 constexpr int kFetch = EMT_COUNT_FETCH;  // pencils a lane fetches per step
 constexpr int kRefillMin = EMT_COUNT_REFILL;  // waiting lanes that start a refill
+constexpr int kFlushUnroll = EMT_FLUSH_UNROLL;  // queue words a flush trip loads together
+static_assert(kFlushUnroll >= 1 && kFlushUnroll <= 4, "flush unroll");
 static_assert(64 * kFetch <= kCountRunCap, "a step's runs must fit the run queue");
 static_assert(kRefillMin >= 1 && kRefillMin <= 64, "refill threshold is a lane count");
 static_assert(64 * kLanePieces <= kPieceCap, "a step's pieces must fit the queue");
@@ -1072,6 +1074,87 @@ __device__ __forceinline__ void line_consts(int4 gi, int dx, int dy, int dz, int
     C = make_float4((float)-ex, (float)-ey, (float)-ez, __uint_as_float(p));
 }
 
+// One queued piece for a flush lane: its run's grains k0 .. k0 + m - 1, the
+// seed slot, the slot's line constants and the piece's grains, all loads
+// issued and none waited on.
+struct Piece {
+    uint32_t k0, m, sl;
+    float4 A, C;
+    float thi;
+    float4 h[kPiece];
+};
+
+// Loads piece (w, lane) of a queue holding qn pieces. A lane past the end
+// (or past word nw - 1) reads run 0 and tests nothing (m = 0): every read
+// stays inside the queue and the sorted grains, which carry kPiece - 1 spare
+// entries past the last one.
+template <bool kFinite>
+__device__ __forceinline__ void piece_load(const CountLds<kFinite> &Q, uint32_t w, uint32_t nw,
+                                           uint32_t qn, unsigned long long upto, int lane,
+                                           const float4 *__restrict__ sgf, Piece &p) {
+    const uint32_t wc = min(w, nw - 1u);
+    const uint32_t s = (w << 6) + (uint32_t)lane;
+    const bool valid = w < nw && s < qn;
+    const unsigned long long word = Q.mask[wc];
+    const uint32_t r = valid ? Q.before[wc] + (uint32_t)__popcll(word & upto) - 1u : 0u;
+    const uint2 rec = Q.run[r];
+    const uint32_t q = valid ? s - (rec.y & 0xfffu) : 0u;  // piece of the run
+    p.sl = (rec.y >> 12) & 0x7fu;
+    p.k0 = rec.x + (uint32_t)kPiece * q;
+    p.m = valid ? min((rec.y >> 19) - (uint32_t)kPiece * q, (uint32_t)kPiece) : 0u;
+    p.A = Q.la[p.sl];
+    p.C = Q.lc[p.sl];
+    p.thi = Q.lthi[p.sl];
+    const float4 *pp = sgf + p.k0;
+#pragma unroll
+    for (int t = 0; t < kPiece; ++t) p.h[t] = pp[t];
+}
+
+// The piece's hits: the FP32 test, the rare band case in int64.
+template <bool kFinite>
+__device__ __forceinline__ uint32_t piece_test(const CountLds<kFinite> &Q, const Piece &p,
+                                               int tol_r, const int4 *__restrict__ sg) {
+    uint32_t n = 0, amb = 0;
+#pragma unroll
+    for (int t = 0; t < kPiece; ++t) {
+        const float4 &h = p.h[t];
+        const float c0 = fmaf(h.y, p.A.z, fmaf(h.z, -p.A.y, p.C.x));
+        const float c1 = fmaf(h.z, p.A.x, fmaf(h.x, -p.A.z, p.C.y));
+        const float c2 = fmaf(h.x, p.A.y, fmaf(h.y, -p.A.x, p.C.z));
+        const float fc = fmaf(c0, c0, fmaf(c1, c1, c2 * c2));
+        bool ok = (uint32_t)t < p.m;
+        if constexpr (kFinite) {
+            const int4 hi = make_int4((int)h.x, (int)h.y, (int)h.z, 0);
+            const int4 Ai = make_int4((int)p.A.x, (int)p.A.y, (int)p.A.z, 0);
+            ok = ok && axial_ok(hi, Ai, Q.pc[p.sl]);
+        }
+        const bool in_lo = fc <= p.A.w, in_hi = fc <= p.thi;
+        n += (ok && in_lo) ? 1u : 0u;
+        amb |= (ok && in_hi && !in_lo) ? (1u << t) : 0u;
+    }
+    if (amb) {
+        // inside the band: decide in int64 from the integer grains (rare)
+        const int dx = (int)p.A.x, dy = (int)p.A.y, dz = (int)p.A.z;
+        const long long D = (long long)dx * dx + (long long)dy * dy + (long long)dz * dz;
+        const long long thr = (long long)tol_r * tol_r * D;
+        const int4 gi = sg[__float_as_uint(p.C.w)];
+#pragma unroll
+        for (int t = 0; t < kPiece; ++t) {
+            if (amb & (1u << t)) {
+                const int4 g = sg[p.k0 + (uint32_t)t];
+                const long long wx = g.x - gi.x, wy = g.y - gi.y, wz = g.z - gi.z;
+                const long long e0 = wy * dz - wz * dy, e1 = wz * dx - wx * dz,
+                                e2 = wx * dy - wy * dx;
+                n += e0 * e0 + e1 * e1 + e2 * e2 <= thr ? 1u : 0u;
+            }
+        }
+    }
+    return n;
+}
+
+// Tests every queued piece, kFlushUnroll queue words per trip: the loads of
+// all of a trip's pieces are issued before any is tested, so a lane has
+// several chains of LDS and grain loads in flight instead of one.
 template <bool kFinite>
 __device__ __forceinline__ void count_flush(CountLds<kFinite> &Q, uint32_t qn, int tol_r,
                                             const int4 *__restrict__ sg,
@@ -1085,59 +1168,15 @@ __device__ __forceinline__ void count_flush(CountLds<kFinite> &Q, uint32_t qn, i
     }
     wave_lds_sync();
     const unsigned long long upto = (2ull << lane) - 1ull;
-    for (uint32_t w = 0; w < nw; ++w) {
-        const uint32_t s = (w << 6) + (uint32_t)lane;
-        const unsigned long long word = Q.mask[w];
-        if (s < qn) {
-            const uint32_t r = Q.before[w] + (uint32_t)__popcll(word & upto) - 1u;
-            const uint2 rec = Q.run[r];
-            const uint32_t q = s - (rec.y & 0xfffu);  // piece of the run
-            const uint32_t sl = (rec.y >> 12) & 0x7fu;
-            const uint32_t k0 = rec.x + (uint32_t)kPiece * q;
-            const uint32_t m = min((rec.y >> 19) - (uint32_t)kPiece * q, (uint32_t)kPiece);
-            const float4 A = Q.la[sl], C = Q.lc[sl];
-            const float thi = Q.lthi[sl];
-            // the sorted grains carry kPiece - 1 spare entries past the
-            // last one, so a piece's loads stay in bounds
-            const float4 *pp = sgf + k0;
-            float4 h[kPiece];
+    for (uint32_t w = 0; w < nw; w += kFlushUnroll) {
+        Piece p[kFlushUnroll];
 #pragma unroll
-            for (int t = 0; t < kPiece; ++t) h[t] = pp[t];
-            uint32_t n = 0, amb = 0;
+        for (int u = 0; u < kFlushUnroll; ++u)
+            piece_load(Q, w + (uint32_t)u, nw, qn, upto, lane, sgf, p[u]);
 #pragma unroll
-            for (int t = 0; t < kPiece; ++t) {
-                const float c0 = fmaf(h[t].y, A.z, fmaf(h[t].z, -A.y, C.x));
-                const float c1 = fmaf(h[t].z, A.x, fmaf(h[t].x, -A.z, C.y));
-                const float c2 = fmaf(h[t].x, A.y, fmaf(h[t].y, -A.x, C.z));
-                const float fc = fmaf(c0, c0, fmaf(c1, c1, c2 * c2));
-                bool ok = (uint32_t)t < m;
-                if constexpr (kFinite) {
-                    const int4 hi = make_int4((int)h[t].x, (int)h[t].y, (int)h[t].z, 0);
-                    const int4 Ai = make_int4((int)A.x, (int)A.y, (int)A.z, 0);
-                    ok = ok && axial_ok(hi, Ai, Q.pc[sl]);
-                }
-                const bool in_lo = fc <= A.w, in_hi = fc <= thi;
-                n += (ok && in_lo) ? 1u : 0u;
-                amb |= (ok && in_hi && !in_lo) ? (1u << t) : 0u;
-            }
-            if (amb) {
-                // inside the band: decide in int64 from the integer grains (rare)
-                const int dx = (int)A.x, dy = (int)A.y, dz = (int)A.z;
-                const long long D = (long long)dx * dx + (long long)dy * dy + (long long)dz * dz;
-                const long long thr = (long long)tol_r * tol_r * D;
-                const int4 gi = sg[__float_as_uint(C.w)];
-#pragma unroll
-                for (int t = 0; t < kPiece; ++t) {
-                    if (amb & (1u << t)) {
-                        const int4 g = sg[k0 + (uint32_t)t];
-                        const long long wx = g.x - gi.x, wy = g.y - gi.y, wz = g.z - gi.z;
-                        const long long e0 = wy * dz - wz * dy, e1 = wz * dx - wx * dz,
-                                        e2 = wx * dy - wy * dx;
-                        n += e0 * e0 + e1 * e1 + e2 * e2 <= thr ? 1u : 0u;
-                    }
-                }
-            }
-            if (n) atomicAdd(&Q.cnt[sl], n);
+        for (int u = 0; u < kFlushUnroll; ++u) {
+            const uint32_t n = piece_test(Q, p[u], tol_r, sg);
+            if (n) atomicAdd(&Q.cnt[p[u].sl], n);
         }
     }
     wave_lds_sync();

@@ -26,6 +26,9 @@
 #ifndef EMT_COUNT_BLOCKS
 #define EMT_COUNT_BLOCKS 1024  // workgroups of the counting kernel
 #endif
+#ifndef EMT_FLUSH_UNROLL
+#define EMT_FLUSH_UNROLL 1  // queue words a flush trip of the counting kernel loads together
+#endif
 #ifndef EMT_COUNT_OCCUPANCY
 #define EMT_COUNT_OCCUPANCY 4  // waves per SIMD the counting kernel is compiled for
 #endif
