@@ -98,6 +98,7 @@ TILE_SPACE = {
     "EMT_COUNT_LANE_PIECES": (8, 16),
     "EMT_COUNT_FETCH": (2, 3, 4),
     "EMT_COUNT_REFILL": (16, 32, 48),
+    "EMT_FLUSH_UNROLL": (1, 2),
     "EMT_CHUNK_SEEDS": (64, 128, 256),
     "EMT_COUNT_BLOCKS": (1024, 2048),
     "EMT_COUNT_OCCUPANCY": (4, 5),
@@ -109,6 +110,7 @@ TILE_COMMENTS = {
     "EMT_COUNT_LANE_PIECES": "queue entries a lane adds per step",
     "EMT_COUNT_FETCH": "cell pencils a lane fetches per step",
     "EMT_COUNT_REFILL": "lanes waiting for a seed before a wave refills",
+    "EMT_FLUSH_UNROLL": "queue words a flush trip loads before testing",
     "EMT_CHUNK_SEEDS": "seeds a wave takes at a time (single views)",
     "EMT_COUNT_BLOCKS": "workgroups of the counting kernel",
     "EMT_COUNT_OCCUPANCY": "waves per SIMD the counting kernel is compiled for",

@@ -24,15 +24,6 @@ namespace {
 #ifndef EMT_DYN_MIN_SEEDS
 #define EMT_DYN_MIN_SEEDS 8000000
 #endif
-#ifndef EMT_MEMBER_LANES
-#define EMT_MEMBER_LANES 4
-#endif
-#ifndef EMT_MEMBER_LANE_CAP
-#define EMT_MEMBER_LANE_CAP 32
-#endif
-#ifndef EMT_MEMBER_SLOT_CAP
-#define EMT_MEMBER_SLOT_CAP 4096
-#endif
 constexpr float kMargin = 4.0f;  // units added to every cell window
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;
@@ -557,42 +548,6 @@ struct Pencil {
     }
 };
 
-// The cylinder predicate |(g_k - g_i) x d|^2 <= r^2 |d|^2, exact.
-// c = g_k x d - g_i x d is formed with 24-bit multiplies in wrapping 32-bit
-// arithmetic: coordinates are in [0, 2^18] and |d_m| < 2^12, so every true
-// component of c is below 2^31 and the wrapped result equals it. |c|^2 is
-// compared in FP32 with a relative guard band of 2^-20 (the FP32 sum of
-// squares is within 5 * 2^-24 of exact); inside the band the test is redone
-// in int64, with the threshold r^2 |d|^2 formed there.
-struct LineTest {
-    uint32_t ex, ey, ez;
-    float tlo, thi;
-
-    __device__ __forceinline__ void init(int4 gi, int dx, int dy, int dz, int r) {
-        ex = (uint32_t)__mul24(gi.y, dz) - (uint32_t)__mul24(gi.z, dy);
-        ey = (uint32_t)__mul24(gi.z, dx) - (uint32_t)__mul24(gi.x, dz);
-        ez = (uint32_t)__mul24(gi.x, dy) - (uint32_t)__mul24(gi.y, dx);
-        const long long D = (long long)dx * dx + (long long)dy * dy + (long long)dz * dz;
-        const float tf = (float)((long long)r * r * D);
-        tlo = tf * (1.0f - 0x1p-20f);
-        thi = tf * (1.0f + 0x1p-20f);
-    }
-};
-
-__device__ __forceinline__ bool cyl_hit(int4 h, int4 A, int4 B, int tol_r) {
-    // A = (dx, dy, dz, tlo), B = (ex, ey, ez, thi)
-    const int c0 = (int)((uint32_t)__mul24(h.y, A.z) - (uint32_t)__mul24(h.z, A.y) - (uint32_t)B.x);
-    const int c1 = (int)((uint32_t)__mul24(h.z, A.x) - (uint32_t)__mul24(h.x, A.z) - (uint32_t)B.y);
-    const int c2 = (int)((uint32_t)__mul24(h.x, A.y) - (uint32_t)__mul24(h.y, A.x) - (uint32_t)B.z);
-    const float f0 = (float)c0, f1 = (float)c1, f2 = (float)c2;
-    const float fc = fmaf(f0, f0, fmaf(f1, f1, f2 * f2));
-    if (fc <= __int_as_float(A.w)) return true;
-    if (fc > __int_as_float(B.w)) return false;
-    const long long cc = (long long)c0 * c0 + (long long)c1 * c1 + (long long)c2 * c2;
-    const long long D = (long long)A.x * A.x + (long long)A.y * A.y + (long long)A.z * A.z;
-    return cc <= (long long)tol_r * tol_r * D;
-}
-
 // Acceptance variants.
 //
 // Finite cylinder: grain k also needs t = g_k.d in [lo, hi], lo = g_i.d - F,
@@ -789,53 +744,13 @@ __global__ void k_member_total(Counters *cnt, const unsigned long long *part64) 
 
 
 // ------------------------------------------------------- count / members
-//
-// One wave takes 64 seeds (count) or candidates (members), one per lane.
-// Each lane walks its own line four pencils per step, but instead of testing
-// the grains of a run itself it appends a run record (first grain, first
-// queue slot, owner lane) to a wave-private queue in LDS and marks the first
-// slot in a bit mask. When the queue fills, the wave tests 64 queued grains
-// per instruction: the run holding slot s is found by counting the marks up
-// to s, the line constants of its owner lane come from LDS, and hits are
-// counted with LDS atomics. Only the cheap walk is divergent across lanes;
-// the predicate work is dense.
 
-constexpr int kSlotCap = EMT_MEMBER_SLOT_CAP;  // queued grain tests per wave
-constexpr int kRunCap = 768;                   // queued runs per wave
-constexpr int kLaneCap = EMT_MEMBER_LANE_CAP;  // grains one lane may queue per step
-static_assert(kSlotCap >= 2 * 64 * kLaneCap && kSlotCap <= 4096, "member queue size");
 constexpr int kWaves = kBlock / 64;
-constexpr int kMaskWords = kSlotCap / 64;
-
-template <bool kFinite>
-struct QueueLds {
-    int4 pa[64];  // dx, dy, dz, tlo
-    int4 pb[64];  // ex, ey, ez, thi
-    int2 pc[kFinite ? 64 : 1];  // finite cylinder: bounds of g_k.d
-    uint32_t cnt[64];
-    uint32_t out_off[64];
-    uint32_t ncap[64];
-    unsigned long long mask[kMaskWords];  // bit s: a run starts at slot s
-    uint32_t before[kMaskWords];          // runs starting before word w
-    uint32_t run_k[kRunCap];              // first grain of the run
-    uint32_t run_tag[kRunCap];            // first slot | owner lane << 16
-};
 
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t *tot) {
-    uint32_t x = v;
-    const int lane = lane_id();
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    *tot = __shfl(x, 63);
-    return x - v;
 }
 
 // Inclusive prefix sum over the 64 lanes with DPP row shifts and row
@@ -851,161 +766,9 @@ __device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t x) {
     return v;
 }
 
-template <bool kFinite>
-__device__ __forceinline__ void flush_queue(QueueLds<kFinite> &Q, uint32_t qn, int tol_r, const int4 *__restrict__ sg,
-                                            uint32_t *__restrict__ members, int lane) {
-    wave_lds_sync();
-    const uint32_t nw = (qn + 63) >> 6;
-    {
-        const uint32_t c = (uint32_t)lane < nw ? (uint32_t)__popcll(Q.mask[lane]) : 0u;
-        uint32_t tot;
-        const uint32_t ex = wave_excl_scan(c, &tot);
-        if ((uint32_t)lane < nw) Q.before[lane] = ex;
-    }
-    wave_lds_sync();
-    const unsigned long long upto = (2ull << lane) - 1ull;  // bits 0..lane
-    for (uint32_t w = 0; w < nw; ++w) {
-        const uint32_t s = (w << 6) + (uint32_t)lane;
-        const unsigned long long word = Q.mask[w];
-        if (s < qn) {
-            const uint32_t r = Q.before[w] + (uint32_t)__popcll(word & upto) - 1u;
-            const uint32_t tag = Q.run_tag[r];
-            const uint32_t kk = Q.run_k[r] + (s - (tag & 0xffffu));
-            const uint32_t sl = tag >> 16;
-            const int4 h = sg[kk];
-            if (cyl_hit(h, Q.pa[sl], Q.pb[sl], tol_r) &&
-                (!kFinite || axial_ok(h, Q.pa[sl], Q.pc[sl]))) {
-                const uint32_t pos = atomicAdd(&Q.cnt[sl], 1u);
-                if (pos < Q.ncap[sl]) members[Q.out_off[sl] + pos] = kk;
-            }
-        }
-    }
-    wave_lds_sync();
-    if ((uint32_t)lane < nw) Q.mask[lane] = 0ull;
-    wave_lds_sync();
-}
-
-template <int kPer, bool kFinite>
-__global__ void __launch_bounds__(kBlock) k_members(DevPtrs d, Caps c, Params P) {
-    __shared__ QueueLds<kFinite> sQ[kWaves];
-    const int lane = lane_id();
-    const int slot = lane / kPer, sub = lane % kPer;
-    constexpr int kItems = 64 / kPer;
-    QueueLds<kFinite> &Q = sQ[threadIdx.x >> 6];
-    const uint32_t nc = d.cnt->n_cand;
-    // nothing to list when the entries overflow their buffer (the call is re-run)
-    const bool skip = d.cnt->err || d.cnt->n_members > c.mem_cap;
-    const unsigned long long n_items = skip ? 0ull : (nc < c.cand_cap ? nc : c.cand_cap);
-    if (lane < kMaskWords) Q.mask[lane] = 0ull;
-    wave_lds_sync();
-    const unsigned long long gw = grid_tid() >> 6, nw = grid_threads() >> 6;
-    for (unsigned long long base = gw * kItems; base < n_items; base += nw * kItems) {
-        const unsigned long long idx = base + (unsigned long long)slot;
-        const bool valid = idx < n_items;
-        uint32_t p = 0, q = 0, v = 0, ncap = 0, off = 0;
-        if (valid) {
-            const Cand cd = d.cand[idx];
-            p = cd.p;
-            q = cd.q;
-            v = cd.v;
-            off = d.mem_off[idx];
-            ncap = ((unsigned long long)off + cd.n <= c.mem_cap) ? cd.n : 0u;
-        }
-        const int4 gi = d.sg[p], gj = d.sg[q];
-        const int dx = gj.x - gi.x, dy = gj.y - gi.y, dz = gj.z - gi.z;
-        LineTest L;
-        L.init(gi, dx, dy, dz, P.r);
-        if (sub == 0) {
-            Q.pa[slot] = make_int4(dx, dy, dz, __float_as_int(L.tlo));
-            Q.pb[slot] = make_int4((int)L.ex, (int)L.ey, (int)L.ez, __float_as_int(L.thi));
-            if constexpr (kFinite) Q.pc[slot] = axial_bounds(gi, dx, dy, dz, P.cyl_ext);
-            Q.cnt[slot] = 0;
-            Q.out_off[slot] = off;
-            Q.ncap[slot] = ncap;
-        }
-        wave_lds_sync();
-        Pencil W;
-        W.init(&d.grids[v], gi, dx, dy, dz, P.r, valid && ncap > 0, sub, kPer,
-               kFinite ? P.cyl_ext : -1);
-        Run s0 = {0, 0}, s1 = {0, 0}, s2 = {0, 0}, s3 = {0, 0};
-        uint32_t qn = 0, nr = 0;
-        for (;;) {
-            // refill the four run slots once all are used up: up to eight
-            // cell_start loads in flight before the first is needed
-            if (s0.k >= s0.e && s1.k >= s1.e && s2.k >= s2.e && s3.k >= s3.e && W.live) {
-                W.fetch(d.cell_start, s0);
-                W.fetch(d.cell_start, s1);
-                W.fetch(d.cell_start, s2);
-                W.fetch(d.cell_start, s3);
-            }
-            uint32_t budget = kLaneCap;
-            const uint32_t l0 = min(s0.e > s0.k ? s0.e - s0.k : 0u, budget);
-            budget -= l0;
-            const uint32_t l1 = min(s1.e > s1.k ? s1.e - s1.k : 0u, budget);
-            budget -= l1;
-            const uint32_t l2 = min(s2.e > s2.k ? s2.e - s2.k : 0u, budget);
-            budget -= l2;
-            const uint32_t l3 = min(s3.e > s3.k ? s3.e - s3.k : 0u, budget);
-            const uint32_t nrun = (l0 > 0) + (l1 > 0) + (l2 > 0) + (l3 > 0);
-            const uint32_t mine = l0 + l1 + l2 + l3;
-            uint32_t tot;
-            const uint32_t packed = wave_excl_scan(mine | (nrun << 16), &tot);
-            if (tot == 0) {
-                if (__ballot(W.live) == 0) break;
-                continue;
-            }
-            uint32_t pos = qn + (packed & 0xffffu);
-            uint32_t ri = nr + (packed >> 16);
-            const uint32_t tag = (uint32_t)slot << 16;
-            if (l0) {
-                Q.run_k[ri] = s0.k;
-                Q.run_tag[ri++] = pos | tag;
-                atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
-                pos += l0;
-                s0.k += l0;
-            }
-            if (l1) {
-                Q.run_k[ri] = s1.k;
-                Q.run_tag[ri++] = pos | tag;
-                atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
-                pos += l1;
-                s1.k += l1;
-            }
-            if (l2) {
-                Q.run_k[ri] = s2.k;
-                Q.run_tag[ri++] = pos | tag;
-                atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
-                pos += l2;
-                s2.k += l2;
-            }
-            if (l3) {
-                Q.run_k[ri] = s3.k;
-                Q.run_tag[ri] = pos | tag;
-                atomicOr(&Q.mask[pos >> 6], 1ull << (pos & 63));
-                s3.k += l3;
-            }
-            qn += tot & 0xffffu;
-            nr += tot >> 16;
-            if (qn > (uint32_t)(kSlotCap - 64 * kLaneCap) || nr > (uint32_t)(kRunCap - 256)) {
-                flush_queue(Q, qn, P.r, d.sg, d.members, lane);
-                qn = 0;
-                nr = 0;
-            }
-        }
-        if (qn) flush_queue(Q, qn, P.r, d.sg, d.members, lane);
-        wave_lds_sync();
-        const uint32_t n = Q.cnt[slot];
-        if (sub == 0 && valid && ncap > 0 && n != ncap) {
-            // the same walk and predicate as the count: never expected;
-            // keep every entry a valid grain index and flag an internal error
-            for (uint32_t t = n; t < ncap; ++t) d.members[off + t] = p;
-            atomicOr(&d.cnt->err, 2u);
-        }
-        wave_lds_sync();
-    }
-}
-
-// Counting with lane refill. A wave owns a chunk of seeds; each lane holds
+// Counting with lane refill (one kernel counts the seeds and, as a second
+// instance, lists the members of the candidates). A wave owns a chunk of
+// seeds; each lane holds
 // two seed slots in LDS. When a lane's walk ends it closes that slot and at
 // once takes the next seed of the chunk into its other slot, so the wave's
 // time is the sum of its lines' work rather than a multiple of the longest
@@ -1036,7 +799,7 @@ static_assert(kPieceWords <= 64 && kPieceCap % 64 == 0, "one mask word per lane"
 static_assert(kPieceCap <= 4096 && kPiece * kLanePieces < 8192, "run record fields");
 static_assert(kPiece >= 1 && (uint32_t)kPiece - 1u <= kSortedSpare, "piece size");
 
-template <bool kFinite>
+template <bool kFinite, bool kEmit = false>
 struct CountLds {
     // line constants per seed slot (floats): d, -(g_i x d), the band
     // [tlo, thi] of the FP32 test, and the sorted position of g_i
@@ -1045,6 +808,10 @@ struct CountLds {
     float lthi[kCountSlots];  // thi
     int2 pc[kFinite ? kCountSlots : 1];  // finite cylinder: bounds of g_k.d
     uint32_t cnt[kCountSlots];
+    // listing the members of candidates: where a slot's grains go, and how
+    // many its list holds (its count)
+    uint32_t out_off[kEmit ? kCountSlots : 1];
+    uint32_t ncap[kEmit ? kCountSlots : 1];
     unsigned long long mask[kPieceWords];  // bit s: a run starts at piece s
     uint32_t before[kPieceWords];          // runs starting before word w
     uint2 run[kCountRunCap];  // first grain; first piece | seed slot << 12 | grains << 19
@@ -1088,8 +855,8 @@ struct Piece {
 // (or past word nw - 1) reads run 0 and tests nothing (m = 0): every read
 // stays inside the queue and the sorted grains, which carry kPiece - 1 spare
 // entries past the last one.
-template <bool kFinite>
-__device__ __forceinline__ void piece_load(const CountLds<kFinite> &Q, uint32_t w, uint32_t nw,
+template <bool kFinite, bool kEmit>
+__device__ __forceinline__ void piece_load(const CountLds<kFinite, kEmit> &Q, uint32_t w, uint32_t nw,
                                            uint32_t qn, unsigned long long upto, int lane,
                                            const float4 *__restrict__ sgf, Piece &p) {
     const uint32_t wc = min(w, nw - 1u);
@@ -1110,9 +877,10 @@ __device__ __forceinline__ void piece_load(const CountLds<kFinite> &Q, uint32_t 
     for (int t = 0; t < kPiece; ++t) p.h[t] = pp[t];
 }
 
-// The piece's hits: the FP32 test, the rare band case in int64.
-template <bool kFinite>
-__device__ __forceinline__ uint32_t piece_test(const CountLds<kFinite> &Q, const Piece &p,
+// The piece's hits as a bit mask over its grains: the FP32 test, the rare
+// band case in int64.
+template <bool kFinite, bool kEmit>
+__device__ __forceinline__ uint32_t piece_test(const CountLds<kFinite, kEmit> &Q, const Piece &p,
                                                int tol_r, const int4 *__restrict__ sg) {
     uint32_t n = 0, amb = 0;
 #pragma unroll
@@ -1129,7 +897,7 @@ __device__ __forceinline__ uint32_t piece_test(const CountLds<kFinite> &Q, const
             ok = ok && axial_ok(hi, Ai, Q.pc[p.sl]);
         }
         const bool in_lo = fc <= p.A.w, in_hi = fc <= p.thi;
-        n += (ok && in_lo) ? 1u : 0u;
+        n |= (ok && in_lo) ? (1u << t) : 0u;
         amb |= (ok && in_hi && !in_lo) ? (1u << t) : 0u;
     }
     if (amb) {
@@ -1145,7 +913,7 @@ __device__ __forceinline__ uint32_t piece_test(const CountLds<kFinite> &Q, const
                 const long long wx = g.x - gi.x, wy = g.y - gi.y, wz = g.z - gi.z;
                 const long long e0 = wy * dz - wz * dy, e1 = wz * dx - wx * dz,
                                 e2 = wx * dy - wy * dx;
-                n += e0 * e0 + e1 * e1 + e2 * e2 <= thr ? 1u : 0u;
+                n |= e0 * e0 + e1 * e1 + e2 * e2 <= thr ? (1u << t) : 0u;
             }
         }
     }
@@ -1155,10 +923,15 @@ __device__ __forceinline__ uint32_t piece_test(const CountLds<kFinite> &Q, const
 // Tests every queued piece, kFlushUnroll queue words per trip: the loads of
 // all of a trip's pieces are issued before any is tested, so a lane has
 // several chains of LDS and grain loads in flight instead of one.
-template <bool kFinite>
-__device__ __forceinline__ void count_flush(CountLds<kFinite> &Q, uint32_t qn, int tol_r,
+// Counting adds a piece's hits to its seed's count with one LDS atomic;
+// listing (kEmit) takes as many positions in the candidate's member list and
+// writes the hit grains' sorted positions there (in any order: the merge
+// treats a list as a set and the fit orders it).
+template <bool kFinite, bool kEmit>
+__device__ __forceinline__ void count_flush(CountLds<kFinite, kEmit> &Q, uint32_t qn, int tol_r,
                                             const int4 *__restrict__ sg,
-                                            const float4 *__restrict__ sgf, int lane) {
+                                            const float4 *__restrict__ sgf,
+                                            uint32_t *__restrict__ members, int lane) {
     wave_lds_sync();
     const uint32_t nw = (qn + 63) >> 6;
     {
@@ -1175,8 +948,22 @@ __device__ __forceinline__ void count_flush(CountLds<kFinite> &Q, uint32_t qn, i
             piece_load(Q, w + (uint32_t)u, nw, qn, upto, lane, sgf, p[u]);
 #pragma unroll
         for (int u = 0; u < kFlushUnroll; ++u) {
-            const uint32_t n = piece_test(Q, p[u], tol_r, sg);
-            if (n) atomicAdd(&Q.cnt[p[u].sl], n);
+            const uint32_t bits = piece_test(Q, p[u], tol_r, sg);
+            if (bits) {
+                const uint32_t n = (uint32_t)__popc(bits);
+                const uint32_t at = atomicAdd(&Q.cnt[p[u].sl], n);
+                if constexpr (kEmit) {
+                    const uint32_t cap = Q.ncap[p[u].sl], base = Q.out_off[p[u].sl];
+                    uint32_t pos = at;
+#pragma unroll
+                    for (int t = 0; t < kPiece; ++t) {
+                        if (bits & (1u << t)) {
+                            if (pos < cap) members[base + pos] = p[u].k0 + (uint32_t)t;
+                            ++pos;
+                        }
+                    }
+                }
+            }
         }
     }
     wave_lds_sync();
@@ -1189,13 +976,22 @@ __device__ __forceinline__ void count_flush(CountLds<kFinite> &Q, uint32_t qn, i
 // compiler then keeps the kernel within 512 / kCountOccupancy VGPRs).
 constexpr int kCountOccupancy = EMT_COUNT_OCCUPANCY;
 
-template <bool kFinite>
+// kEmit: the members stage. The same walk and test over the candidates
+// instead of the seeds, listing each candidate's grains (its count is known:
+// the list must come out exactly that long).
+template <bool kFinite, bool kEmit>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kCountOccupancy)))
 k_count(DevPtrs d, Caps c, Params P) {
-    __shared__ CountLds<kFinite> sQ[kWaves];
+    __shared__ CountLds<kFinite, kEmit> sQ[kWaves];
     const int lane = lane_id();
-    CountLds<kFinite> &Q = sQ[threadIdx.x >> 6];
-    const uint32_t n_items = d.cnt->n_seeds_ok;
+    CountLds<kFinite, kEmit> &Q = sQ[threadIdx.x >> 6];
+    uint32_t n_items = d.cnt->n_seeds_ok;
+    if constexpr (kEmit) {
+        // nothing to list when the entries overflow their buffer (the call
+        // is re-run)
+        const bool skip = d.cnt->err || d.cnt->n_members > c.mem_cap;
+        n_items = skip ? 0u : min(d.cnt->n_cand, c.cand_cap);
+    }
     if (lane < kPieceWords) Q.mask[lane] = 0ull;
     wave_lds_sync();
     unsigned long long tests = 0, hits = 0;
@@ -1212,9 +1008,13 @@ k_count(DevPtrs d, Caps c, Params P) {
     const uint32_t xcd = blockIdx.x & 7u;
     const uint32_t per = ((n_items + 7u) / 8u + 63u) & ~63u;
     const uint32_t wpx = max(1u, (gridDim.x >> 3) * kWaves);
-    uint32_t chunk = gw * kChunkSeeds;
+    // chunks shrink (to a quarter wave at least) when there are too few
+    // items to give every wave a full one: a long walk per lane is better
+    // than idle waves
+    const uint32_t cs = min((uint32_t)kChunkSeeds, max(16u, (n_items + nwv - 1u) / nwv));
+    uint32_t chunk = gw * cs;
     uint32_t next = dyn ? 0u : min(chunk, n_items);
-    uint32_t end = dyn ? 0u : min(n_items, chunk + kChunkSeeds);
+    uint32_t end = dyn ? 0u : min(n_items, chunk + cs);
     bool more = true;
     bool have = false;
     bool pend0 = false, pend1 = false;  // slot closed, count not yet written
@@ -1228,20 +1028,33 @@ k_count(DevPtrs d, Caps c, Params P) {
     for (int f = 0; f < kFetch; ++f) run[f] = Run{0, 0};
     uint32_t qn = 0, nr = 0;
     // counts of closed slots are final after a flush: write them, free slots
-    auto finalize = [&]() {
-        // seed_n is 0 from the seed pass; only counts that reach the
-        // threshold are written (a few percent: scattered 4-byte stores of
-        // every count would each cost a partial line write)
-        if (pend0) {
-            const uint32_t n = Q.cnt[lane];
+    auto close = [&](int sl, uint32_t idx, uint32_t th) {
+        const uint32_t n = Q.cnt[sl];
+        if constexpr (kEmit) {
+            // the same walk and predicate as the count: a list of another
+            // length is never expected; keep every entry a valid grain
+            // index and flag an internal error
+            const uint32_t cap = Q.ncap[sl];
+            if (cap > 0 && n != cap) {
+                const uint32_t p0 = d.cand[idx].p;
+                for (uint32_t t = n; t < cap; ++t) d.members[Q.out_off[sl] + t] = p0;
+                atomicOr(&d.cnt->err, 2u);
+            }
+        } else {
+            // seed_n is 0 from the seed pass; only counts that reach the
+            // threshold are written (a few percent: scattered 4-byte stores
+            // of every count would each cost a partial line write)
             hits += n;
-            if (n >= th0) d.seed_n[idx0] = n;
+            if (n >= th) d.seed_n[idx] = n;
+        }
+    };
+    auto finalize = [&]() {
+        if (pend0) {
+            close(lane, idx0, th0);
             pend0 = false;
         }
         if (pend1) {
-            const uint32_t n = Q.cnt[lane + 64];
-            hits += n;
-            if (n >= th1) d.seed_n[idx1] = n;
+            close(lane + 64, idx1, th1);
             pend1 = false;
         }
         wave_lds_sync();
@@ -1252,12 +1065,12 @@ k_count(DevPtrs d, Caps c, Params P) {
                 if (next >= end && more)
                     more = xcd_grab(d.grab, xcd, per, n_items, wpx, 64u, 4096u, next, end);
             } else {
-                more = chunk + nwv * kChunkSeeds < n_items;
+                more = chunk + nwv * cs < n_items;
                 if (next >= end && more) {
-                    chunk += nwv * kChunkSeeds;
+                    chunk += nwv * cs;
                     next = chunk;
-                    end = min(n_items, chunk + kChunkSeeds);
-                    more = chunk + nwv * kChunkSeeds < n_items;
+                    end = min(n_items, chunk + cs);
+                    more = chunk + nwv * cs < n_items;
                 }
             }
             // take the next seeds into free slots. Setting up a seed (its
@@ -1274,8 +1087,19 @@ k_count(DevPtrs d, Caps c, Params P) {
             if (take) {
                 const uint32_t idx = next + rank;
                 cur = pend0 ? lane + 64 : lane;
-                const uint2 pq = d.seeds[idx];
-                const uint32_t v = d.view_of[pq.x];
+                uint2 pq;
+                uint32_t v;
+                if constexpr (kEmit) {
+                    const Cand cd = d.cand[idx];
+                    pq = make_uint2(cd.p, cd.q);
+                    v = cd.v;
+                    const uint32_t off = d.mem_off[idx];
+                    Q.out_off[cur] = off;
+                    Q.ncap[cur] = ((unsigned long long)off + cd.n <= c.mem_cap) ? cd.n : 0u;
+                } else {
+                    pq = d.seeds[idx];
+                    v = d.view_of[pq.x];
+                }
                 const int4 gi = d.sg[pq.x], gj = d.sg[pq.y];
                 const int dx = gj.x - gi.x, dy = gj.y - gi.y, dz = gj.z - gi.z;
                 const uint32_t th = seed_threshold(dx, dy, dz, P);
@@ -1325,7 +1149,7 @@ k_count(DevPtrs d, Caps c, Params P) {
             // room first: test what is queued if this step's runs do not fit
             if (qn + (tot & 0xffffu) > (uint32_t)kPieceCap ||
                 nr + (tot >> 16) > (uint32_t)kCountRunCap) {
-                count_flush(Q, qn, P.r, d.sg, d.sgf, lane);
+                count_flush(Q, qn, P.r, d.sg, d.sgf, d.members, lane);
                 qn = 0;
                 nr = 0;
                 finalize();
@@ -1360,7 +1184,7 @@ k_count(DevPtrs d, Caps c, Params P) {
             const uint32_t n_blocked = (uint32_t)__popcll(__ballot(blocked));
             const bool all_done = __ballot(have) == 0 && next >= end && !more;
             if (all_done || n_blocked > 16) {
-                if (qn) count_flush(Q, qn, P.r, d.sg, d.sgf, lane);
+                if (qn) count_flush(Q, qn, P.r, d.sg, d.sgf, d.members, lane);
                 qn = 0;
                 nr = 0;
                 finalize();
@@ -1368,8 +1192,10 @@ k_count(DevPtrs d, Caps c, Params P) {
             }
         }
     }
-    add_spread(d.part64, 2, wave_sum(tests));
-    add_spread(d.part64, 3, wave_sum(hits));
+    if constexpr (!kEmit) {
+        add_spread(d.part64, 2, wave_sum(tests));
+        add_spread(d.part64, 3, wave_sum(hits));
+    }
 }
 
 // Candidates in seed order: position from the flag scan of seed_n; their
@@ -2511,9 +2337,9 @@ void launch_seeds(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t 
 
 void launch_count(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
     if (P.cyl_ext >= 0)
-        k_count<true><<<kCountBlocks, kBlock, 0, s>>>(d, c, P);
+        k_count<true, false><<<kCountBlocks, kBlock, 0, s>>>(d, c, P);
     else
-        k_count<false><<<kCountBlocks, kBlock, 0, s>>>(d, c, P);
+        k_count<false, false><<<kCountBlocks, kBlock, 0, s>>>(d, c, P);
 }
 
 void launch_candidates(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
@@ -2525,12 +2351,11 @@ void launch_candidates(const DevPtrs &d, const Caps &c, const Params &P, hipStre
 void launch_members(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
     scan_excl(d.cand_n, &d.cnt->n_cand, c.cand_cap, d.scan_part, d.mem_off, &d.cnt->n_members, s);
     k_member_total<<<1, 64, 0, s>>>(d.cnt, d.part64);
-    const uint32_t nb =
-        blocks_for((unsigned long long)EMT_MEMBER_LANES * c.cand_cap, kPersistentBlocks);
+    // the counting kernel's walk and test, listing the grains of each candidate
     if (P.cyl_ext >= 0)
-        k_members<EMT_MEMBER_LANES, true><<<nb, kBlock, 0, s>>>(d, c, P);
+        k_count<true, true><<<kCountBlocks, kBlock, 0, s>>>(d, c, P);
     else
-        k_members<EMT_MEMBER_LANES, false><<<nb, kBlock, 0, s>>>(d, c, P);
+        k_count<false, true><<<kCountBlocks, kBlock, 0, s>>>(d, c, P);
 }
 
 void launch_merge_init(const DevPtrs &d, const Caps &c, const Params &, hipStream_t s) {
