@@ -249,7 +249,8 @@ size_t grain_bytes(size_t n) {
            bytes_of<unsigned long long>(n);
 }
 size_t seed_bytes(size_t n) {
-    return bytes_of<uint2>(n) + bytes_of<uint32_t>(n) + bytes_of<uint32_t>(n + 1);
+    return bytes_of<uint2>(n) + bytes_of<uint32_t>(n) + bytes_of<uint32_t>(n / 32 + 1) +
+           bytes_of<uint32_t>(n / 32 + 2);
 }
 size_t cand_bytes(size_t n) {
     return bytes_of<Cand>(n) + bytes_of<unsigned long long>(n) + 4 * bytes_of<uint32_t>(n + 1) +
@@ -270,7 +271,7 @@ size_t view_bytes(size_t n) {
 // the scan scratch serves every scan: cells, anchors, seeds, candidates
 uint32_t scan_words(const Caps &c) {
     return std::max<uint32_t>(std::max<uint32_t>(c.n_cells, c.cand_cap),
-                              std::max<uint32_t>((uint32_t)c.seed_cap, c.n_total)) + 1;
+                              std::max<uint32_t>((uint32_t)(c.seed_cap / 32 + 1), c.n_total)) + 1;
 }
 
 // Make every buffer hold the capacities in c, carve the pointer table, and
@@ -302,7 +303,8 @@ int ensure(emt_ctx *ctx, Caps &c) {
         char *p = (char *)ctx->seed_buf.p;
         d.seeds = carve<uint2>(p, n);
         d.seed_n = carve<uint32_t>(p, n);
-        d.cand_pos = carve<uint32_t>(p, n + 1);
+        d.pass = carve<uint32_t>(p, n / 32 + 1);
+        d.pass_pos = carve<uint32_t>(p, n / 32 + 2);
         ctx->cap_seeds = c.seed_cap;
     }
     if (c.cand_cap > ctx->cap_cand || !ctx->cand_buf.p) {

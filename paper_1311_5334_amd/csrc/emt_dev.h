@@ -93,7 +93,7 @@ struct Counters {
     uint32_t rounds;
     uint32_t n_fp64;
     uint32_t err;
-    uint32_t pad1;
+    uint32_t pass_words;  // words of the candidate bit mask: ceil(n_seeds_ok / 32)
     unsigned long long seeds64;    // exact number of seeds
     unsigned long long members64;  // exact number of member entries
 };
@@ -143,7 +143,9 @@ struct DevPtrs {
     uint32_t *seed_off;   // N + 1
     uint2 *seeds;         // seed_cap
     uint32_t *seed_n;     // seed_cap: count if >= n_min, else 0
-    uint32_t *cand_pos;   // seed_cap + 1
+    uint32_t *pass;       // seed_cap / 32 + 1 words: bit s % 32 of word s / 32
+                          // set when seed s reaches its threshold
+    uint32_t *pass_pos;   // seed_cap / 32 + 2: candidates in the words before
     Cand *cand;           // cand_cap
     unsigned long long *key;  // cand_cap
     uint32_t *cand_n;     // cand_cap + 1

@@ -109,20 +109,20 @@ __device__ __forceinline__ uint32_t scan_len(const uint32_t *n_dev, uint32_t n_c
     return n < n_cap ? n : n_cap;
 }
 
-template <bool kFlag>
+template <bool kPopc>
 __device__ __forceinline__ uint32_t scan_in(const uint32_t *in, uint32_t i) {
     const uint32_t v = in[i];
-    return kFlag ? (v != 0u ? 1u : 0u) : v;
+    return kPopc ? (uint32_t)__popc(v) : v;
 }
 
-template <bool kFlag>
+template <bool kPopc>
 __global__ void __launch_bounds__(kBlock) k_scan_part(const uint32_t *in, const uint32_t *n_dev,
                                                       uint32_t n_cap, uint32_t *part) {
     const uint32_t n = scan_len(n_dev, n_cap);
     const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
     uint32_t s = 0;
     for (int i = 0; i < kScanItems; ++i)
-        if (base + i < n) s += scan_in<kFlag>(in, base + i);
+        if (base + i < n) s += scan_in<kPopc>(in, base + i);
     uint32_t tot;
     block_excl_scan(s, &tot);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_part_scan(uint32_t *part, uint3
     }
 }
 
-template <bool kFlag>
+template <bool kPopc>
 __global__ void __launch_bounds__(kBlock) k_scan_apply(const uint32_t *in, const uint32_t *n_dev,
                                                        uint32_t n_cap, const uint32_t *part,
                                                        uint32_t *out) {
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const uint32_t *in, const
     uint32_t v[kScanItems];
     uint32_t s = 0;
     for (int i = 0; i < kScanItems; ++i) {
-        v[i] = (base + i < n) ? scan_in<kFlag>(in, base + i) : 0u;
+        v[i] = (base + i < n) ? scan_in<kPopc>(in, base + i) : 0u;
         s += v[i];
     }
     uint32_t tot;
@@ -171,14 +171,14 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const uint32_t *in, const
 }
 
 // out[i] = sum of in[0..i) for i <= n, n = min(*n_dev, n_cap) (n_cap if no
-// n_dev); *total_out = out[n]. With kFlag the summands are (in[i] != 0).
-template <bool kFlag = false>
+// n_dev); *total_out = out[n]. With kPopc the summands are popcount(in[i]).
+template <bool kPopc = false>
 void scan_excl(const uint32_t *in, const uint32_t *n_dev, uint32_t n_cap, uint32_t *part,
                uint32_t *out, uint32_t *total_out, hipStream_t s) {
     const uint32_t nb = n_cap / kScanTile + 1;
-    k_scan_part<kFlag><<<nb, kBlock, 0, s>>>(in, n_dev, n_cap, part);
+    k_scan_part<kPopc><<<nb, kBlock, 0, s>>>(in, n_dev, n_cap, part);
     k_scan_part_scan<<<1, kBlock, 0, s>>>(part, nb, n_dev, n_cap, out, total_out);
-    k_scan_apply<kFlag><<<nb, kBlock, 0, s>>>(in, n_dev, n_cap, part, out);
+    k_scan_apply<kPopc><<<nb, kBlock, 0, s>>>(in, n_dev, n_cap, part, out);
 }
 
 // ------------------------------------------------------------------- bin
@@ -639,6 +639,12 @@ __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
     const uint32_t n_total = d.desc->n_total;
     // the write pass has nothing to do when the seeds overflow their buffer
     if (kWrite && d.cnt->n_seeds_ok == 0) return;
+    if constexpr (kWrite) {
+        // the candidate bit mask starts clear; the counting kernel sets the
+        // bits of the seeds that reach their threshold
+        const uint32_t nwd = d.cnt->pass_words;
+        for (uint32_t w = grid_tid(); w < nwd; w += grid_threads()) d.pass[w] = 0u;
+    }
     unsigned long long wave_total = 0;  // count pass: seeds of this wave's anchors
     for (uint32_t p = gw; p < n_total; p += nw) {
         const uint32_t v = d.view_of[p];
@@ -687,9 +693,6 @@ __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
                             // the seed's i (the fit's origin and key order)
                             if (slot < c.seed_cap) {
                                 d.seeds[slot] = h.w > g.w ? make_uint2(p, q) : make_uint2(q, p);
-                                // counts below the threshold stay 0: the
-                                // counting kernel writes only the others
-                                d.seed_n[slot] = 0u;
                             }
                         }
                         base += (uint32_t)__popcll(m);
@@ -726,6 +729,7 @@ __global__ void k_seed_total(Counters *cnt, const unsigned long long *part64,
     const uint32_t n = s > 0xffffffffull ? 0xffffffffu : (uint32_t)s;
     cnt->n_seeds = n;
     cnt->n_seeds_ok = n <= seed_cap ? n : 0u;
+    cnt->pass_words = (uint32_t)(((unsigned long long)cnt->n_seeds_ok + 31ull) / 32ull);
 }
 
 // Likewise for the member entries (the scan of candidate counts): a total
@@ -1041,11 +1045,14 @@ k_count(DevPtrs d, Caps c, Params P) {
                 atomicOr(&d.cnt->err, 2u);
             }
         } else {
-            // seed_n is 0 from the seed pass; only counts that reach the
-            // threshold are written (a few percent: scattered 4-byte stores
-            // of every count would each cost a partial line write)
+            // only counts that reach the threshold are written, with their
+            // bit in the candidate mask (a few percent: scattered 4-byte
+            // stores of every count would each cost a partial line write)
             hits += n;
-            if (n >= th) d.seed_n[idx] = n;
+            if (n >= th) {
+                d.seed_n[idx] = n;
+                atomicOr(&d.pass[idx >> 5], 1u << (idx & 31u));
+            }
         }
     };
     auto finalize = [&]() {
@@ -1198,36 +1205,45 @@ k_count(DevPtrs d, Caps c, Params P) {
     }
 }
 
-// Candidates in seed order: position from the flag scan of seed_n; their
-// counts (for the member offsets); and the seeds and candidates of each
-// view, from the offsets (views are contiguous in anchor order, so in seed
-// and in candidate order too).
+// Candidates among seeds [0, s), s <= n_seeds_ok: the scan of the mask's
+// popcounts up to word s / 32, plus the set bits below s in that word.
+__device__ __forceinline__ uint32_t cand_before(const DevPtrs &d, uint32_t s) {
+    const uint32_t w = s >> 5, b = s & 31u;
+    return d.pass_pos[w] + (b ? (uint32_t)__popc(d.pass[w] & ((1u << b) - 1u)) : 0u);
+}
+
+// Candidates in seed order, one mask word per thread: positions from the
+// scan of the words' popcounts; their counts (for the member offsets); and
+// the seeds and candidates of each view (views are contiguous in anchor
+// order, so in seed and in candidate order too).
 __global__ void __launch_bounds__(kBlock) k_cand_scatter(DevPtrs d, Caps c, Params P) {
     const uint32_t ns = d.cnt->n_seeds_ok;
     for (uint32_t v = grid_tid(); v < d.desc->n_views; v += grid_threads()) {
         const uint32_t g0 = d.grids[v].grain_off, g1 = g0 + d.grids[v].n;
         const uint32_t s0 = d.seed_off[g0], s1 = d.seed_off[g1];
         d.view_seeds[v] = s1 - s0;
-        d.view_cand[v] = d.cand_pos[min(s1, ns)] - d.cand_pos[min(s0, ns)];
+        d.view_cand[v] = cand_before(d, min(s1, ns)) - cand_before(d, min(s0, ns));
     }
     unsigned long long listed = 0;  // member entries of the listed candidates
-    for (uint32_t s = grid_tid(); s < ns; s += grid_threads()) {
-        const uint32_t n = d.seed_n[s];
-        if (!n) continue;
-        const uint32_t pos = d.cand_pos[s];
-        if (pos >= c.cand_cap) continue;
-        listed += n;
-        const uint2 pq = d.seeds[s];
-        Cand cd;
-        cd.p = pq.x;
-        cd.q = pq.y;
-        cd.n = n;
-        cd.v = d.view_of[pq.x];
-        d.cand[pos] = cd;
-        d.cand_n[pos] = n;
-        const int4 gi = d.sg[pq.x], gj = d.sg[pq.y];
-        if (P.thr_num) d.cand_thr[pos] = seed_threshold(gj.x - gi.x, gj.y - gi.y, gj.z - gi.z, P);
-        d.key[pos] = cand_key(n, (uint32_t)gi.w, (uint32_t)gj.w);
+    const uint32_t nwd = d.cnt->pass_words;
+    for (uint32_t w = grid_tid(); w < nwd; w += grid_threads()) {
+        uint32_t bits = d.pass[w];
+        for (uint32_t pos = d.pass_pos[w]; bits && pos < c.cand_cap; ++pos, bits &= bits - 1u) {
+            const uint32_t s = (w << 5) | (uint32_t)(__ffs(bits) - 1);
+            const uint32_t n = d.seed_n[s];
+            listed += n;
+            const uint2 pq = d.seeds[s];
+            Cand cd;
+            cd.p = pq.x;
+            cd.q = pq.y;
+            cd.n = n;
+            cd.v = d.view_of[pq.x];
+            d.cand[pos] = cd;
+            d.cand_n[pos] = n;
+            const int4 gi = d.sg[pq.x], gj = d.sg[pq.y];
+            if (P.thr_num) d.cand_thr[pos] = seed_threshold(gj.x - gi.x, gj.y - gi.y, gj.z - gi.z, P);
+            d.key[pos] = cand_key(n, (uint32_t)gi.w, (uint32_t)gj.w);
+        }
     }
     add_spread(d.part64, 1, wave_sum(listed));
 }
@@ -1422,7 +1438,7 @@ __global__ void __launch_bounds__(kBlock) k_round(DevPtrs d, Params P, int round
 // First candidate of view v: candidates are listed in seed order, and a
 // view's seeds are contiguous.
 __device__ __forceinline__ uint32_t view_first_cand(const DevPtrs &d, uint32_t v, uint32_t ns) {
-    return d.cand_pos[min(d.seed_off[d.grids[v].grain_off], ns)];
+    return cand_before(d, min(d.seed_off[d.grids[v].grain_off], ns));
 }
 
 // Candidates of different views share no grain, so the rounds the grid-wide
@@ -2343,9 +2359,9 @@ void launch_count(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t 
 }
 
 void launch_candidates(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
-    scan_excl<true>(d.seed_n, &d.cnt->n_seeds_ok, (uint32_t)c.seed_cap, d.scan_part, d.cand_pos,
-                    &d.cnt->n_cand, s);
-    k_cand_scatter<<<blocks_for(c.seed_cap, kPersistentBlocks), kBlock, 0, s>>>(d, c, P);
+    const uint32_t words = (uint32_t)(c.seed_cap / 32 + 1);
+    scan_excl<true>(d.pass, &d.cnt->pass_words, words, d.scan_part, d.pass_pos, &d.cnt->n_cand, s);
+    k_cand_scatter<<<blocks_for(words, kPersistentBlocks), kBlock, 0, s>>>(d, c, P);
 }
 
 void launch_members(const DevPtrs &d, const Caps &c, const Params &P, hipStream_t s) {
