@@ -297,6 +297,8 @@ def main() -> int:
     ap.add_argument("--prebuilt", metavar="DIR", help="directory written by --build-tiles")
     ap.add_argument("--table", default=TABLE)
     ap.add_argument("--report", default=None, help="also write a markdown summary here")
+    ap.add_argument("--lib", default=None,
+                    help="--cells: time this build of the library instead of the in-tree one")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))
     if args.time_lib:
@@ -312,7 +314,7 @@ def main() -> int:
     from paper_1311_5334_amd import emt, synth
 
     assert torch.cuda.is_available(), "the autotuner needs a GPU"
-    emt.load()
+    emt.load(args.lib or emt.LIB_PATH)
     cands = list(itertools.product(CX, CY, CZ))
     best, lines = {}, []
     t_start = time.time()

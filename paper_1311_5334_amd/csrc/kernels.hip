@@ -621,6 +621,25 @@ __device__ __forceinline__ bool xcd_grab(uint32_t *grab, uint32_t xcd, uint32_t 
     return next != 0xffffffffu;
 }
 
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Inclusive prefix sum over the 64 lanes with DPP row shifts and row
+// broadcasts (no LDS traffic).
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t x) {
+    uint32_t v = x;
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
 // ----------------------------------------------------------------- seeds
 //
 // One wave per anchor grain p (a sorted position); lanes take the (y, z)
@@ -632,6 +651,9 @@ __device__ __forceinline__ bool xcd_grab(uint32_t *grab, uint32_t xcd, uint32_t 
 // anchor order, so each view's seeds are contiguous.
 template <bool kWrite>
 __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
+    // per wave: the first flat element of each row, and sorted position
+    // minus that (so that grain = dk[r] + element)
+    __shared__ uint32_t s_rows[kBlock / 64][2][64];
     const int lane = lane_id();
     const uint32_t gw = grid_tid() >> 6, nw = grid_threads() >> 6;
     const int R1 = P.R - 1;
@@ -669,6 +691,13 @@ __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
             const int nyr = y1 - y0 + 1;
             const int nrows = nyr * (z1 - z0 + 1);
             const int row_p = (zp - z0) * nyr + (yp - y0);
+            // the rows' grains are taken as one flat range, 64 at a time:
+            // lane L tests element b + L, found in row r, the last row
+            // whose first element is at or below it (a binary search over
+            // the rows' starts in LDS), so every lane has a grain whatever
+            // the row lengths
+            uint32_t *ex_s = s_rows[threadIdx.x >> 6][0];
+            uint32_t *dk_s = s_rows[threadIdx.x >> 6][1];
             for (int rb = row_p; rb < nrows; rb += 64) {
                 const int rr = rb + lane;
                 uint32_t k0 = 0, k1 = 0;
@@ -678,10 +707,24 @@ __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
                     k0 = max(d.cell_start[row + x0], p + 1);
                     k1 = d.cell_start[row + x1 + 1];
                 }
-                for (uint32_t q = k0; q < k1; ++q) {
+                const uint32_t len = k1 > k0 ? k1 - k0 : 0u;
+                const uint32_t incl = wave_incl_scan_dpp(len);
+                const uint32_t T = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+                wave_lds_sync();  // the previous block's readers are done
+                ex_s[lane] = incl - len;
+                dk_s[lane] = k0 - (incl - len);
+                wave_lds_sync();
+                for (uint32_t b = 0; b < T; b += 64) {
+                    const uint32_t i = b + (uint32_t)lane;
+                    uint32_t r = 0;
+#pragma unroll
+                    for (uint32_t step = 32; step > 0; step >>= 1)
+                        r = ex_s[r + step] <= i ? r + step : r;
+                    bool ok = i < T;
+                    const uint32_t q = ok ? dk_s[r] + i : p;
                     const int4 h = d.sg[q];
                     const int ex = h.x - g.x, ey = h.y - g.y, ez = h.z - g.z;
-                    bool ok = abs(ex) <= R1 && abs(ey) <= R1 && abs(ez) <= R1;
+                    ok = ok && abs(ex) <= R1 && abs(ey) <= R1 && abs(ez) <= R1;
                     const int D = ok ? ex * ex + ey * ey + ez * ez : 0;
                     ok = ok && D > 0 && D < R2;
                     if (kWrite) {
@@ -691,19 +734,13 @@ __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
                                 (unsigned long long)base + (unsigned long long)__popcll(m & lanes_below());
                             // stored lower input index first: that grain is
                             // the seed's i (the fit's origin and key order)
-                            if (slot < c.seed_cap) {
+                            if (slot < c.seed_cap)
                                 d.seeds[slot] = h.w > g.w ? make_uint2(p, q) : make_uint2(q, p);
-                            }
                         }
                         base += (uint32_t)__popcll(m);
                     } else {
                         mine += ok ? 1u : 0u;
                     }
-                }
-                // lanes that left the row loop early missed later ballots:
-                // the running offset only grows, so the largest is current
-                if (kWrite) {
-                    for (int o = 32; o > 0; o >>= 1) base = max(base, __shfl_xor(base, o));
                 }
             }
         }
@@ -751,25 +788,6 @@ __global__ void k_member_total(Counters *cnt, const unsigned long long *part64) 
 
 constexpr int kWaves = kBlock / 64;
 
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Inclusive prefix sum over the 64 lanes with DPP row shifts and row
-// broadcasts (no LDS traffic).
-__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t x) {
-    uint32_t v = x;
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
-    return v;
-}
-
 // Counting with lane refill (one kernel counts the seeds and, as a second
 // instance, lists the members of the candidates). A wave owns a chunk of
 // seeds; each lane holds
@@ -808,8 +826,8 @@ struct CountLds {
     // line constants per seed slot (floats): d, -(g_i x d), the band
     // [tlo, thi] of the FP32 test, and the sorted position of g_i
     float4 la[kCountSlots];  // dx, dy, dz, tlo
-    float4 lc[kCountSlots];  // -ex, -ey, -ez, (bits) sorted position of g_i
-    float lthi[kCountSlots];  // thi
+    float4 lc[kCountSlots];  // -ex, -ey, -ez, thi
+    uint32_t lp[kCountSlots];  // sorted position of g_i (the int64 test)
     int2 pc[kFinite ? kCountSlots : 1];  // finite cylinder: bounds of g_k.d
     uint32_t cnt[kCountSlots];
     // listing the members of candidates: where a slot's grains go, and how
@@ -830,8 +848,8 @@ struct CountLds {
 // tlo = (r - 1/8)^2 |d|^2 and certainly outside above thi = (r + 1/8)^2
 // |d|^2, both widened by 2^-20 for the rounding of the squares (tlo < 0
 // when r <= 1/8); in between the test is redone in int64.
-__device__ __forceinline__ void line_consts(int4 gi, int dx, int dy, int dz, int r, uint32_t p,
-                                            float4 &A, float &thi_out, float4 &C) {
+__device__ __forceinline__ void line_consts(int4 gi, int dx, int dy, int dz, int r, float4 &A,
+                                            float4 &C) {
     const long long D = (long long)dx * dx + (long long)dy * dy + (long long)dz * dz;
     const double sd = sqrt((double)D);
     const double lo = (double)r * sd - 0.125 * sd, hi = (double)r * sd + 0.125 * sd;
@@ -841,8 +859,7 @@ __device__ __forceinline__ void line_consts(int4 gi, int dx, int dy, int dz, int
     const long long ey = (long long)gi.z * dx - (long long)gi.x * dz;
     const long long ez = (long long)gi.x * dy - (long long)gi.y * dx;
     A = make_float4((float)dx, (float)dy, (float)dz, tlo);
-    thi_out = thi;
-    C = make_float4((float)-ex, (float)-ey, (float)-ez, __uint_as_float(p));
+    C = make_float4((float)-ex, (float)-ey, (float)-ez, thi);
 }
 
 // One queued piece for a flush lane: its run's grains k0 .. k0 + m - 1, the
@@ -851,7 +868,6 @@ __device__ __forceinline__ void line_consts(int4 gi, int dx, int dy, int dz, int
 struct Piece {
     uint32_t k0, m, sl;
     float4 A, C;
-    float thi;
     float4 h[kPiece];
 };
 
@@ -875,7 +891,6 @@ __device__ __forceinline__ void piece_load(const CountLds<kFinite, kEmit> &Q, ui
     p.m = valid ? min((rec.y >> 19) - (uint32_t)kPiece * q, (uint32_t)kPiece) : 0u;
     p.A = Q.la[p.sl];
     p.C = Q.lc[p.sl];
-    p.thi = Q.lthi[p.sl];
     const float4 *pp = sgf + p.k0;
 #pragma unroll
     for (int t = 0; t < kPiece; ++t) p.h[t] = pp[t];
@@ -900,7 +915,7 @@ __device__ __forceinline__ uint32_t piece_test(const CountLds<kFinite, kEmit> &Q
             const int4 Ai = make_int4((int)p.A.x, (int)p.A.y, (int)p.A.z, 0);
             ok = ok && axial_ok(hi, Ai, Q.pc[p.sl]);
         }
-        const bool in_lo = fc <= p.A.w, in_hi = fc <= p.thi;
+        const bool in_lo = fc <= p.A.w, in_hi = fc <= p.C.w;
         n |= (ok && in_lo) ? (1u << t) : 0u;
         amb |= (ok && in_hi && !in_lo) ? (1u << t) : 0u;
     }
@@ -909,7 +924,7 @@ __device__ __forceinline__ uint32_t piece_test(const CountLds<kFinite, kEmit> &Q
         const int dx = (int)p.A.x, dy = (int)p.A.y, dz = (int)p.A.z;
         const long long D = (long long)dx * dx + (long long)dy * dy + (long long)dz * dz;
         const long long thr = (long long)tol_r * tol_r * D;
-        const int4 gi = sg[__float_as_uint(p.C.w)];
+        const int4 gi = sg[Q.lp[p.sl]];
 #pragma unroll
         for (int t = 0; t < kPiece; ++t) {
             if (amb & (1u << t)) {
@@ -1119,11 +1134,10 @@ k_count(DevPtrs d, Caps c, Params P) {
                 }
                 if constexpr (kFinite) Q.pc[cur] = axial_bounds(gi, dx, dy, dz, P.cyl_ext);
                 float4 A, C;
-                float thi;
-                line_consts(gi, dx, dy, dz, P.r, pq.x, A, thi, C);
+                line_consts(gi, dx, dy, dz, P.r, A, C);
                 Q.la[cur] = A;
                 Q.lc[cur] = C;
-                Q.lthi[cur] = thi;
+                Q.lp[cur] = pq.x;
                 Q.cnt[cur] = 0;
                 W.init(&d.grids[v], gi, dx, dy, dz, P.r, true, 0, 1, kFinite ? P.cyl_ext : -1);
                 have = true;
