@@ -94,10 +94,10 @@ constexpr int kTunedCells[8][3] = {{
 TILE_TABLE = os.path.join(HERE, "csrc", "tile_table.h")
 # candidate values of each tile constant (see csrc/tile_table.h)
 TILE_SPACE = {
-    "EMT_COUNT_PIECE": (1, 2, 4),
-    "EMT_COUNT_LANE_PIECES": (8, 16),
-    "EMT_COUNT_FETCH": (2, 3, 4),
-    "EMT_COUNT_REFILL": (16, 32, 48),
+    "EMT_COUNT_PIECE": (2, 3, 4),
+    "EMT_COUNT_LANE_PIECES": (16, 24, 32),
+    "EMT_COUNT_FETCH": (5, 6, 8),
+    "EMT_COUNT_REFILL": (24, 32, 48),
     "EMT_FLUSH_UNROLL": (1, 2),
     "EMT_CHUNK_SEEDS": (64, 128, 256),
     "EMT_COUNT_BLOCKS": (1024, 2048),

@@ -846,15 +846,16 @@ struct CountLds {
 // so each component is within 0.06 |d| of the exact one and |c| within
 // 0.104 |d|. A grain is certainly inside when the FP32 |c|^2 is at most
 // tlo = (r - 1/8)^2 |d|^2 and certainly outside above thi = (r + 1/8)^2
-// |d|^2, both widened by 2^-20 for the rounding of the squares (tlo < 0
-// when r <= 1/8); in between the test is redone in int64.
+// |d|^2, both widened by 2^-20 (tlo < 0 when r = 0); in between the test is
+// redone in int64. The widening covers the rounding of the FP32 sum of
+// squares (within 5 * 2^-24 relative) and of the FP32 products forming tlo
+// and thi (|d|^2 < 2^26 rounded, a square, two products: within 4 * 2^-24).
 __device__ __forceinline__ void line_consts(int4 gi, int dx, int dy, int dz, int r, float4 &A,
                                             float4 &C) {
-    const long long D = (long long)dx * dx + (long long)dy * dy + (long long)dz * dz;
-    const double sd = sqrt((double)D);
-    const double lo = (double)r * sd - 0.125 * sd, hi = (double)r * sd + 0.125 * sd;
-    const float tlo = lo > 0.0 ? (float)(lo * lo * (1.0 - 0x1p-20)) : -1.0f;
-    const float thi = (float)(hi * hi * (1.0 + 0x1p-20));
+    const float Df = (float)(dx * dx + dy * dy + dz * dz);  // |d| < 2^12: exact in int32
+    const float rlo = (float)r - 0.125f, rhi = (float)r + 0.125f;  // exact
+    const float tlo = r > 0 ? rlo * rlo * Df * (1.0f - 0x1p-20f) : -1.0f;
+    const float thi = rhi * rhi * Df * (1.0f + 0x1p-20f);
     const long long ex = (long long)gi.y * dz - (long long)gi.z * dy;
     const long long ey = (long long)gi.z * dx - (long long)gi.x * dz;
     const long long ez = (long long)gi.x * dy - (long long)gi.y * dx;

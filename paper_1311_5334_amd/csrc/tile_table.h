@@ -2,23 +2,26 @@
 // the cell budget per grain, chosen by paper_1311_5334_amd/autotune.py
 // --tiles from timings of the whole path; -D on the compiler line overrides
 // each value.
-//   starting tiles {'EMT_COUNT_PIECE': 4, 'EMT_COUNT_LANE_PIECES': 8, 'EMT_COUNT_FETCH': 4, 'EMT_COUNT_REFILL': 32, 'EMT_CHUNK_SEEDS': 128, 'EMT_COUNT_BLOCKS': 1024, 'EMT_COUNT_OCCUPANCY': 4, 'EMT_MERGE_WIDE': 16, 'EMT_CELLS_PER_GRAIN': 4}: c2 1.190 ms, c5x8 45.040 ms, c3x16 6.319 ms
-//   chosen tiles {'EMT_COUNT_PIECE': 4, 'EMT_COUNT_LANE_PIECES': 16, 'EMT_COUNT_FETCH': 4, 'EMT_COUNT_REFILL': 32, 'EMT_CHUNK_SEEDS': 128, 'EMT_COUNT_BLOCKS': 1024, 'EMT_COUNT_OCCUPANCY': 4, 'EMT_MERGE_WIDE': 16, 'EMT_CELLS_PER_GRAIN': 4} (each constant's best one-at-a-time variation)
-//   14 builds timed
+//   starting tiles {'EMT_COUNT_PIECE': 3, 'EMT_COUNT_LANE_PIECES': 24, 'EMT_COUNT_FETCH': 6, 'EMT_COUNT_REFILL': 32, 'EMT_FLUSH_UNROLL': 1, 'EMT_CHUNK_SEEDS': 128, 'EMT_COUNT_BLOCKS': 1024, 'EMT_COUNT_OCCUPANCY': 5, 'EMT_MERGE_WIDE': 16, 'EMT_CELLS_PER_GRAIN': 4}: c2 1.054 ms, c5x8 36.628 ms, c3x16 5.363 ms
+//   chosen tiles {'EMT_COUNT_PIECE': 3, 'EMT_COUNT_LANE_PIECES': 24, 'EMT_COUNT_FETCH': 6, 'EMT_COUNT_REFILL': 32, 'EMT_FLUSH_UNROLL': 1, 'EMT_CHUNK_SEEDS': 128, 'EMT_COUNT_BLOCKS': 1024, 'EMT_COUNT_OCCUPANCY': 5, 'EMT_MERGE_WIDE': 16, 'EMT_CELLS_PER_GRAIN': 4} (each constant's best one-at-a-time variation)
+//   16 builds timed
 #ifndef EMT_TILE_TABLE_H
 #define EMT_TILE_TABLE_H
 
 #ifndef EMT_COUNT_PIECE
-#define EMT_COUNT_PIECE 4  // grains a flush lane tests per queue entry
+#define EMT_COUNT_PIECE 3  // grains a flush lane tests per queue entry
 #endif
 #ifndef EMT_COUNT_LANE_PIECES
-#define EMT_COUNT_LANE_PIECES 16  // queue entries a lane adds per step
+#define EMT_COUNT_LANE_PIECES 24  // queue entries a lane adds per step
 #endif
 #ifndef EMT_COUNT_FETCH
-#define EMT_COUNT_FETCH 4  // cell pencils a lane fetches per step
+#define EMT_COUNT_FETCH 6  // cell pencils a lane fetches per step
 #endif
 #ifndef EMT_COUNT_REFILL
 #define EMT_COUNT_REFILL 32  // lanes waiting for a seed before a wave refills
+#endif
+#ifndef EMT_FLUSH_UNROLL
+#define EMT_FLUSH_UNROLL 1  // queue words a flush trip loads before testing
 #endif
 #ifndef EMT_CHUNK_SEEDS
 #define EMT_CHUNK_SEEDS 128  // seeds a wave takes at a time (single views)
@@ -26,11 +29,8 @@
 #ifndef EMT_COUNT_BLOCKS
 #define EMT_COUNT_BLOCKS 1024  // workgroups of the counting kernel
 #endif
-#ifndef EMT_FLUSH_UNROLL
-#define EMT_FLUSH_UNROLL 1  // queue words a flush trip of the counting kernel loads together
-#endif
 #ifndef EMT_COUNT_OCCUPANCY
-#define EMT_COUNT_OCCUPANCY 4  // waves per SIMD the counting kernel is compiled for
+#define EMT_COUNT_OCCUPANCY 5  // waves per SIMD the counting kernel is compiled for
 #endif
 #ifndef EMT_MERGE_WIDE
 #define EMT_MERGE_WIDE 16  // grid-wide merge rounds at most before the per-view tails
