@@ -43,8 +43,8 @@ N_BUCKETS = 8
 EDGE0 = 0.75  # grains per 1000 um^3 at the lower edge of bucket 1; doubling
 TUNED = range(1, 6)  # buckets swept (up to 24 per 1000 um^3); the others copy the nearest
 CX = (100, 150, 200, 250, 350, 500)
-CY = (400, 500, 750, 1000, 1500)
-CZ = (200, 300, 500, 800)
+CY = (500, 750, 1000, 1500, 2000, 3000)
+CZ = (200, 300, 500, 800, 1200)
 DEFAULT = (250, 750, 500)
 
 
