@@ -51,7 +51,8 @@ struct BatchDesc {
 // Cell edges by grain density: bucket b holds views with at least
 // kCellEdge0 * 2^(b-1) grains per 1000 um^3 (b = 0: below kCellEdge0).
 // Per-XCD seed-range counters of the counting kernel, 64 B apart.
-constexpr int kGrabWords = 8 * 16;
+// two sets (counting, then listing the candidates' members), 16 words per XCD
+constexpr int kGrabWords = 2 * 8 * 16;
 constexpr int kCellBuckets = 8;
 // Partial sums of four 64-bit totals (seeds, member entries, counting tests,
 // counting hits): kPartSlots counters per total, one 128-byte line apart, so
@@ -158,7 +159,7 @@ struct DevPtrs {
     uint8_t *used;        // N
     unsigned long long *owner;  // N
     uint32_t *undecided;  // per merge round: candidates it left undecided
-    uint32_t *grab;       // kGrabWords: seed-range counters of the counting kernel
+    uint32_t *grab;       // kGrabWords: item-range counters of the counting kernel
     uint32_t *act;        // cand_cap: undecided candidates handed to the tail
     uint32_t *act2;       // cand_cap
     uint32_t *acc;        // cand_cap

@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(kBlock) k_zero(Counters *cnt, unsigned long lo
         Counters z = {};
         *cnt = z;
     }
-    if (tid < kGrabWords) grab[tid] = 0;
+    for (uint32_t i = tid; i < (uint32_t)kGrabWords; i += grid_threads()) grab[i] = 0;
     for (uint32_t i = tid; i < (uint32_t)kPartWords; i += grid_threads()) part64[i] = 0;
     for (uint32_t v = tid; v < n_views; v += grid_threads()) {
         view_seeds[v] = 0;
@@ -1022,7 +1022,9 @@ k_count(DevPtrs d, Caps c, Params P) {
     // from its own XCD's range, so that XCD's L2 holds the grains of those
     // views only, and moves on to the other ranges when its own is used up;
     // grabs shrink as a range empties, so the waves finish together. (Grabs
-    // cost a device-scope atomic each, too many for a single view.)
+    // cost a device-scope atomic each, too many for a single view.) The
+    // listing instance has range counters of its own: the counting one
+    // leaves its counters used up.
     const bool dyn = n_items > (uint32_t)EMT_DYN_MIN_SEEDS;
     const uint32_t gw = grid_tid() >> 6, nwv = grid_threads() >> 6;
     const uint32_t xcd = blockIdx.x & 7u;
@@ -1086,7 +1088,8 @@ k_count(DevPtrs d, Caps c, Params P) {
         {
             if (dyn) {
                 if (next >= end && more)
-                    more = xcd_grab(d.grab, xcd, per, n_items, wpx, 64u, 4096u, next, end);
+                    more = xcd_grab(d.grab + (kEmit ? 8 * 16 : 0), xcd, per, n_items, wpx, 64u,
+                                    4096u, next, end);
             } else {
                 more = chunk + nwv * cs < n_items;
                 if (next >= end && more) {

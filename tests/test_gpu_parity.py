@@ -312,6 +312,33 @@ def test_config5_group_properties_and_alone_equals_batch(emt):
             assert len(b["tracks"]) > 1000
 
 
+def test_config5_batch_of_32_equals_views_alone(emt):
+    """The benchmark's call: 32 dense c5 views, over 8 M candidates, so the
+    counting kernel takes its items in per-XCD grabs both when counting the
+    seeds and when listing the candidates' members. Views tracked alone
+    (fewer items, fixed chunks) must give byte-identical tracks and grains
+    and the same candidates (i, j, n)."""
+    views = [synth.make_c5(i).xyz for i in range(32)]
+    picks = (0, 13, 31)
+
+    def rows(c):
+        return c[np.lexsort((c[:, 1], c[:, 0], c[:, 2]))]
+
+    with emt.Tracker(device=0, flags=emt.EMT_F_STATS | emt.EMT_F_CANDIDATES) as t:
+        batch = t(views)
+        st = t.stats()
+        _say(f"c5 x32: {st['n_seeds']} seeds, {st['n_candidates']} candidates")
+        assert st["n_candidates"] > 8_000_000
+        cand_b = {k: rows(t.candidates(k)) for k in picks}
+        for k in picks:
+            a = t([views[k]])[0]
+            b = batch[k]
+            assert len(b["tracks"]) > 1000
+            assert a["tracks"].tobytes() == b["tracks"].tobytes()
+            assert np.array_equal(a["grains"], b["grains"])
+            assert np.array_equal(rows(t.candidates(0)), cand_b[k])
+
+
 def test_config5_dense_crop_matches_oracle(emt, oracle_mod):
     v = synth.make_c5(5)
     x = v.xyz
