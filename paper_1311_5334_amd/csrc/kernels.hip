@@ -1590,21 +1590,34 @@ __global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, 
 // ------------------------------------------------------------------- fit
 
 // Accepted candidates into the list of tracks (any order: tracks are ranked
-// by key afterwards) and the track count of each view. A workgroup counts its
-// accepted candidates first and reserves their slots with one atomic; a
-// wave adds to a view's count once for its lanes of that view (a wave's
-// candidates are consecutive, so nearly always of one view).
+// by key afterwards) and the track count of each view. A thread takes four
+// consecutive candidates with one 32-bit load of their status bytes (the
+// array is padded to 256 bytes). A workgroup counts its accepted candidates
+// first and reserves their slots with one atomic; a wave adds to a view's
+// count once for its candidates of the view of its first accepted one (a
+// wave's candidates are consecutive, so nearly always of one view).
+__device__ __forceinline__ uint32_t accepted4(const DevPtrs &d, uint32_t q, uint32_t nc) {
+    if (4ull * q >= nc) return 0u;
+    const uint32_t w = reinterpret_cast<const uint32_t *>(d.status)[q];
+    uint32_t bits = 0;
+#pragma unroll
+    for (uint32_t t = 0; t < 4; ++t)
+        bits |= (((w >> (8 * t)) & 0xffu) == kAccepted && 4 * q + t < nc) ? (1u << t) : 0u;
+    return bits;
+}
+
 __global__ void __launch_bounds__(kBlock) k_collect(DevPtrs d, Caps c) {
     __shared__ uint32_t s_cnt, s_base;
     const Counters *cn = d.cnt;
     const uint32_t nc = cn->err ? 0u : min(cn->n_cand, c.cand_cap);
+    const uint32_t nq = (nc + 3u) / 4u;
     const int lane = lane_id();
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
-    for (uint32_t b = blockIdx.x * blockDim.x; b < nc; b += grid_threads()) {
-        const uint32_t i = b + threadIdx.x;
-        const unsigned long long m = __ballot(i < nc && d.status[i] == kAccepted);
-        if (lane == 0 && m) atomicAdd(&s_cnt, (uint32_t)__popcll(m));
+    // block-uniform loops: every lane of a wave takes part in its scans
+    for (uint32_t b = blockIdx.x * blockDim.x; b < nq; b += grid_threads()) {
+        const uint32_t n = wave_sum((uint32_t)__popc(accepted4(d, b + threadIdx.x, nc)));
+        if (lane == 0 && n) atomicAdd(&s_cnt, n);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1612,22 +1625,31 @@ __global__ void __launch_bounds__(kBlock) k_collect(DevPtrs d, Caps c) {
         s_cnt = 0;
     }
     __syncthreads();
-    for (uint32_t b = blockIdx.x * blockDim.x; b < nc; b += grid_threads()) {
-        const uint32_t i = b + threadIdx.x;
-        const bool a = i < nc && d.status[i] == kAccepted;
-        const unsigned long long m = __ballot(a);
-        if (!m) continue;
+    for (uint32_t b = blockIdx.x * blockDim.x; b < nq; b += grid_threads()) {
+        const uint32_t q = b + threadIdx.x;
+        uint32_t bits = accepted4(d, q, nc);
+        const uint32_t k = (uint32_t)__popc(bits);
+        const uint32_t incl = wave_incl_scan_dpp(k);
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        if (tot == 0) continue;
         uint32_t w = 0;
-        if (lane == 0) w = atomicAdd(&s_cnt, (uint32_t)__popcll(m));
+        if (lane == 0) w = atomicAdd(&s_cnt, tot);
         w = (uint32_t)__shfl((int)w, 0);
-        const uint32_t v = a ? d.cand[i].v : 0u;
-        const int first = __ffsll((long long)m) - 1;
-        const uint32_t v0 = (uint32_t)__shfl((int)v, first);
-        if (a) {
-            d.acc[s_base + w + (uint32_t)__popcll(m & lanes_below())] = i;
-            if (v != v0) atomicAdd(&d.view_ntr[v], 1u);
+        const int first = __ffsll((long long)__ballot(bits != 0)) - 1;
+        const uint32_t v_own = bits ? d.cand[4 * q + (uint32_t)(__ffs(bits) - 1)].v : 0u;
+        const uint32_t v0 = (uint32_t)__shfl((int)v_own, first);
+        uint32_t pos = s_base + w + incl - k, same = 0;
+        while (bits) {
+            const uint32_t i = 4 * q + (uint32_t)(__ffs(bits) - 1);
+            bits &= bits - 1u;
+            d.acc[pos++] = i;
+            const uint32_t v = d.cand[i].v;
+            if (v == v0)
+                ++same;
+            else
+                atomicAdd(&d.view_ntr[v], 1u);
         }
-        const uint32_t same = (uint32_t)__popcll(__ballot(a && v == v0));
+        same = wave_sum(same);
         if (lane == first) atomicAdd(&d.view_ntr[v0], same);
     }
 }
@@ -1647,14 +1669,29 @@ __global__ void __launch_bounds__(kBlock) k_view_offsets(DevPtrs d) {
     if (threadIdx.x == 0) d.view_tr_off[n_views] = carry;
 }
 
+// Tracks grouped by view: a wave takes its slots of the view of its lane 0
+// with one atomic on that view's cursor (a view's cursor hit once per track
+// serialises in L2), other views one atomic per track.
 __global__ void __launch_bounds__(kBlock) k_group(DevPtrs d, unsigned long long *gkey) {
     const uint32_t na = d.cnt->n_acc;
-    for (uint32_t a = grid_tid(); a < na; a += grid_threads()) {
-        const uint32_t ci = d.acc[a];
-        const uint32_t v = d.cand[ci].v;
-        const uint32_t pos = d.view_tr_off[v] + atomicAdd(&d.view_cursor[v], 1u);
-        d.grouped[pos] = ci;
-        gkey[pos] = d.key[ci];
+    const int lane = lane_id();
+    for (uint32_t b = blockIdx.x * blockDim.x; b < na; b += grid_threads()) {
+        const uint32_t a = b + threadIdx.x;
+        const bool ok = a < na;  // false for lane 0 only if for the whole wave
+        const uint32_t ci = ok ? d.acc[a] : 0u;
+        const uint32_t v = ok ? d.cand[ci].v : 0u;
+        const uint32_t v0 = (uint32_t)__shfl((int)v, 0);
+        const unsigned long long same = __ballot(ok && v == v0);
+        uint32_t base = 0;
+        if (lane == 0 && same) base = atomicAdd(&d.view_cursor[v0], (uint32_t)__popcll(same));
+        base = (uint32_t)__shfl((int)base, 0);
+        if (ok) {
+            const uint32_t at = v == v0 ? base + (uint32_t)__popcll(same & lanes_below())
+                                        : atomicAdd(&d.view_cursor[v], 1u);
+            const uint32_t pos = d.view_tr_off[v] + at;
+            d.grouped[pos] = ci;
+            gkey[pos] = d.key[ci];
+        }
     }
 }
 
