@@ -714,32 +714,44 @@ __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
                 ex_s[lane] = incl - len;
                 dk_s[lane] = k0 - (incl - len);
                 wave_lds_sync();
-                for (uint32_t b = 0; b < T; b += 64) {
-                    const uint32_t i = b + (uint32_t)lane;
+                // the grain of flat element i (the anchor itself past the end)
+                auto grain_of = [&](uint32_t i) -> uint32_t {
                     uint32_t r = 0;
 #pragma unroll
                     for (uint32_t step = 32; step > 0; step >>= 1)
                         r = ex_s[r + step] <= i ? r + step : r;
-                    bool ok = i < T;
-                    const uint32_t q = ok ? dk_s[r] + i : p;
-                    const int4 h = d.sg[q];
+                    return i < T ? dk_s[r] + i : p;
+                };
+                auto pairs = [&](const int4 &h, bool ok) {
                     const int ex = h.x - g.x, ey = h.y - g.y, ez = h.z - g.z;
                     ok = ok && abs(ex) <= R1 && abs(ey) <= R1 && abs(ez) <= R1;
                     const int D = ok ? ex * ex + ey * ey + ez * ez : 0;
-                    ok = ok && D > 0 && D < R2;
+                    return ok && D > 0 && D < R2;
+                };
+                auto write = [&](bool ok, const int4 &h, uint32_t q) {
+                    const unsigned long long m = __ballot(ok);
+                    if (ok) {
+                        const unsigned long long slot =
+                            (unsigned long long)base + (unsigned long long)__popcll(m & lanes_below());
+                        // stored lower input index first: that grain is the
+                        // seed's i (the fit's origin and key order)
+                        if (slot < c.seed_cap)
+                            d.seeds[slot] = h.w > g.w ? make_uint2(p, q) : make_uint2(q, p);
+                    }
+                    base += (uint32_t)__popcll(m);
+                };
+                // two elements a lane per trip: their row searches and grain
+                // loads are in flight together
+                for (uint32_t b = 0; b < T; b += 128) {
+                    const uint32_t i0 = b + (uint32_t)lane, i1 = i0 + 64;
+                    const uint32_t q0 = grain_of(i0), q1 = grain_of(i1);
+                    const int4 h0 = d.sg[q0], h1 = d.sg[q1];
+                    const bool ok0 = pairs(h0, i0 < T), ok1 = pairs(h1, i1 < T);
                     if (kWrite) {
-                        const unsigned long long m = __ballot(ok);
-                        if (ok) {
-                            const unsigned long long slot =
-                                (unsigned long long)base + (unsigned long long)__popcll(m & lanes_below());
-                            // stored lower input index first: that grain is
-                            // the seed's i (the fit's origin and key order)
-                            if (slot < c.seed_cap)
-                                d.seeds[slot] = h.w > g.w ? make_uint2(p, q) : make_uint2(q, p);
-                        }
-                        base += (uint32_t)__popcll(m);
+                        write(ok0, h0, q0);
+                        write(ok1, h1, q1);
                     } else {
-                        mine += ok ? 1u : 0u;
+                        mine += (ok0 ? 1u : 0u) + (ok1 ? 1u : 0u);
                     }
                 }
             }
