@@ -691,11 +691,11 @@ __global__ void __launch_bounds__(kBlock) k_seeds(DevPtrs d, Caps c, Params P) {
             const int nyr = y1 - y0 + 1;
             const int nrows = nyr * (z1 - z0 + 1);
             const int row_p = (zp - z0) * nyr + (yp - y0);
-            // the rows' grains are taken as one flat range, 64 at a time:
-            // lane L tests element b + L, found in row r, the last row
-            // whose first element is at or below it (a binary search over
-            // the rows' starts in LDS), so every lane has a grain whatever
-            // the row lengths
+            // the rows' grains are taken as one flat range: lane L tests
+            // elements b + L and b + 64 + L of each trip, each found in row
+            // r, the last row whose first element is at or below it (a
+            // binary search over the rows' starts in LDS), so every lane has
+            // grains whatever the row lengths
             uint32_t *ex_s = s_rows[threadIdx.x >> 6][0];
             uint32_t *dk_s = s_rows[threadIdx.x >> 6][1];
             for (int rb = row_p; rb < nrows; rb += 64) {
