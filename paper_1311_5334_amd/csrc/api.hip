@@ -245,8 +245,7 @@ int mapped(emt_ctx *ctx, T *&host, T *&dev, size_t &cap, size_t n) {
 // layout).
 size_t grain_bytes(size_t n) {
     return bytes_of<int32_t>(3 * n) + 4 * bytes_of<uint32_t>(n) + bytes_of<uint32_t>(n + 1) +
-           2 * bytes_of<int4>(n + kSortedSpare) + bytes_of<uint8_t>(n) +
-           bytes_of<unsigned long long>(n);
+           2 * bytes_of<int4>(n + kSortedSpare) + bytes_of<unsigned long long>(n);
 }
 size_t seed_bytes(size_t n) {
     return bytes_of<uint2>(n) + bytes_of<uint32_t>(n) + bytes_of<uint32_t>(n / 32 + 1) +
@@ -292,7 +291,6 @@ int ensure(emt_ctx *ctx, Caps &c) {
         d.seed_off = carve<uint32_t>(p, n + 1);
         d.sg = carve<int4>(p, n + kSortedSpare);
         d.sgf = carve<float4>(p, n + kSortedSpare);
-        d.used = carve<uint8_t>(p, n);
         d.owner = carve<unsigned long long>(p, n);
         ctx->cap_n = (uint32_t)n;
     }

@@ -156,7 +156,6 @@ struct DevPtrs {
     uint8_t *taken;       // mem_cap
     uint8_t *status;      // cand_cap
     uint32_t *mcount;     // cand_cap
-    uint8_t *used;        // N
     unsigned long long *owner;  // N
     uint32_t *undecided;  // per merge round: candidates it left undecided
     uint32_t *grab;       // kGrabWords: item-range counters of the counting kernel

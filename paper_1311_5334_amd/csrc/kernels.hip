@@ -1320,7 +1320,6 @@ __global__ void __launch_bounds__(kBlock) k_merge_init(DevPtrs d, Caps c) {
     }
     const uint32_t n_total = d.desc->n_total;
     for (uint32_t g = grid_tid(); g < n_total; g += grid_threads()) {
-        d.used[g] = 0;
         d.owner[g] = ~0ull;
     }
     for (uint32_t e = grid_tid(); e < nm; e += grid_threads()) d.taken[e] = 0;
@@ -1339,11 +1338,15 @@ __global__ void __launch_bounds__(kBlock) k_merge_init(DevPtrs d, Caps c) {
 // down, so the keys of a newer round lie below every older value and no
 // clearing pass is needed between rounds (keys use 60 bits: n, i and j are
 // below 2^20 each).
-// A reservation: the owner word keeps the smallest key offered to it in a
-// round. It only decreases during a round, so a value read at or below key
-// means an equal or better reservation is already there and the atomic
-// would change nothing; most grains are offered to many candidates, and the
-// read spares most of the atomics.
+// A grain's owner word is ~0 while nobody has reserved it, 0 once an
+// accepted candidate has taken it (no key is 0: a seed's i and j differ),
+// and otherwise the smallest key offered to it. So one load tells whether a
+// grain is still unused and who holds it, and a reservation can never
+// displace a taken grain.
+// A reservation: the word only decreases during a round, so a value read at
+// or below key means an equal or better reservation (or the grain's taking)
+// is already there and the atomic would change nothing; most grains are
+// offered to many candidates, and the read spares most of the atomics.
 __device__ __forceinline__ void reserve(unsigned long long *owner, unsigned long long key) {
     if (*owner > key) atomicMin(owner, key);
 }
@@ -1412,35 +1415,33 @@ __global__ void __launch_bounds__(kBlock) k_round(DevPtrs d, Params P, int round
                 uint32_t unused = 0;
                 if (round > 0) {
                     for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup)
-                        unused += d.used[d.members[e]] ? 0u : 1u;
+                        unused += d.owner[d.members[e]] != 0ull ? 1u : 0u;
                     unused = group_sum8(unused);
                 }
                 if (round > 0 && unused < cand_min(d, P, ci)) {
                     if (sub == 0) d.status[ci] = kRejected;
                 } else {
-                    for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
-                        const uint32_t k = d.members[e];
-                        if (round == 0 || !d.used[k]) reserve(&d.owner[k], key);
-                    }
+                    // a taken grain's word (0) is below every key: untouched
+                    for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup)
+                        reserve(&d.owner[d.members[e]], key);
                 }
             } else {  // decide
                 uint32_t unused = 0, lost = 0;
                 for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
-                    const uint32_t k = d.members[e];
-                    if (!d.used[k]) {
-                        ++unused;
-                        lost |= d.owner[k] != key ? 1u : 0u;
-                    }
+                    const unsigned long long o = d.owner[d.members[e]];
+                    unused += o != 0ull ? 1u : 0u;
+                    lost |= (o != 0ull && o != key) ? 1u : 0u;
                 }
                 unused = group_sum8(unused);
                 lost = group_sum8(lost);
                 if (unused < cand_min(d, P, ci)) {
                     if (sub == 0) d.status[ci] = kRejected;
                 } else if (lost == 0) {
+                    // every unused grain is this candidate's (owner == key)
                     for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
                         const uint32_t k = d.members[e];
-                        if (!d.used[k]) {
-                            d.used[k] = 1;
+                        if (d.owner[k] != 0ull) {
+                            d.owner[k] = 0ull;
                             d.taken[e] = 1;
                         }
                     }
@@ -1525,7 +1526,7 @@ __global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, 
             uint32_t unused = 0;
             for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
                 const uint32_t k = d.members[e];
-                if (!d.used[k]) {
+                if (d.owner[k] != 0ull) {
                     ++unused;
                     d.owner[k] = ~0ull;
                 }
@@ -1541,10 +1542,8 @@ __global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, 
             if (d.status[ci] != kUndecided) continue;
             const unsigned long long key = d.key[ci];
             const uint32_t e0 = d.mem_off[ci], e1 = e0 + d.cand[ci].n;
-            for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
-                const uint32_t k = d.members[e];
-                if (!d.used[k]) reserve(&d.owner[k], key);
-            }
+            for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup)
+                reserve(&d.owner[d.members[e]], key);
         }
         __threadfence_block();
         __syncthreads();
@@ -1556,11 +1555,9 @@ __global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, 
             const uint32_t e0 = d.mem_off[ci], e1 = e0 + d.cand[ci].n;
             uint32_t unused = 0, lost = 0;
             for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
-                const uint32_t k = d.members[e];
-                if (!d.used[k]) {
-                    ++unused;
-                    lost |= d.owner[k] != key ? 1u : 0u;
-                }
+                const unsigned long long o = d.owner[d.members[e]];
+                unused += o != 0ull ? 1u : 0u;
+                lost |= (o != 0ull && o != key) ? 1u : 0u;
             }
             unused = group_sum8(unused);
             lost = group_sum8(lost);
@@ -1569,8 +1566,8 @@ __global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, 
             } else if (lost == 0) {
                 for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
                     const uint32_t k = d.members[e];
-                    if (!d.used[k]) {
-                        d.used[k] = 1;
+                    if (d.owner[k] != 0ull) {
+                        d.owner[k] = 0ull;
                         d.taken[e] = 1;
                     }
                 }
