@@ -113,7 +113,9 @@ __host__ __device__ inline unsigned long long cand_key(uint32_t n, uint32_t i,
            ((unsigned long long)i << 20) | (unsigned long long)j;
 }
 
-enum : uint8_t { kUndecided = 0, kAccepted = 1, kRejected = 2 };
+// kCertain: undecided, but sure to be accepted (it already holds n_min of
+// its grains); it has taken those and waits for the others to be settled.
+enum : uint8_t { kUndecided = 0, kAccepted = 1, kRejected = 2, kCertain = 3 };
 
 // Results, written by the last kernel straight into mapped pinned host
 // memory (device-side addresses of host buffers).

@@ -1383,6 +1383,50 @@ __device__ __forceinline__ void flush_list(uint32_t *s_buf, uint32_t *s_cnt, uin
     __syncthreads();
 }
 
+// The decide phase for one candidate (its eight-lane group; every lane
+// returns the same). Unused grains are those whose owner word is not 0; the
+// candidate holds the ones whose word is its key. Fewer unused grains than
+// its threshold: rejected. Holding every unused grain: accepted with them.
+// Holding at least its threshold but not all: it is sure to be accepted,
+// since no undecided candidate before it wants a grain it holds, so those
+// grains are still unused when its turn comes in the one-by-one reading; it
+// takes them now (kCertain) and waits for the others, taking each as it comes
+// to hold it. A grain taken early is one a later candidate would have lost
+// anyway, so nothing else changes. Returns whether it stays undecided.
+__device__ __forceinline__ bool decide(const DevPtrs &d, const Params &P, uint32_t ci,
+                                       unsigned long long key, uint32_t e0, uint32_t e1,
+                                       int sub) {
+    const bool certain = d.status[ci] == kCertain;
+    uint32_t unused = 0, held = 0, lost = 0;
+    for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
+        const unsigned long long o = d.owner[d.members[e]];
+        unused += o != 0ull ? 1u : 0u;
+        held += o == key ? 1u : 0u;
+        lost |= (o != 0ull && o != key) ? 1u : 0u;
+    }
+    unused = group_sum8(unused);
+    held = group_sum8(held);
+    lost = group_sum8(lost);
+    const uint32_t need = cand_min(d, P, ci);
+    if (!certain && unused < need) {
+        if (sub == 0) d.status[ci] = kRejected;
+        return false;
+    }
+    if (lost != 0 && !certain && held < need) return true;
+    for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
+        const uint32_t k = d.members[e];
+        if (d.owner[k] == key) {
+            d.owner[k] = 0ull;
+            d.taken[e] = 1;
+        }
+    }
+    if (sub == 0) {
+        d.mcount[ci] += held;
+        d.status[ci] = lost == 0 ? kAccepted : kCertain;
+    }
+    return lost != 0;
+}
+
 template <int kPhase>
 __global__ void __launch_bounds__(kBlock) k_round(DevPtrs d, Params P, int round) {
     __shared__ uint32_t s_buf[kPhase == 1 ? kListBuf : 1];
@@ -1403,7 +1447,7 @@ __global__ void __launch_bounds__(kBlock) k_round(DevPtrs d, Params P, int round
         bool live = slot < n;
         if (live) {
             ci = round == 0 ? slot : list[slot];
-            live = round == 0 || d.status[ci] == kUndecided;
+            live = round == 0 || d.status[ci] == kUndecided || d.status[ci] == kCertain;
         }
         bool still = false;
         if (live) {
@@ -1418,7 +1462,7 @@ __global__ void __launch_bounds__(kBlock) k_round(DevPtrs d, Params P, int round
                         unused += d.owner[d.members[e]] != 0ull ? 1u : 0u;
                     unused = group_sum8(unused);
                 }
-                if (round > 0 && unused < cand_min(d, P, ci)) {
+                if (round > 0 && unused < cand_min(d, P, ci) && d.status[ci] != kCertain) {
                     if (sub == 0) d.status[ci] = kRejected;
                 } else {
                     // a taken grain's word (0) is below every key: untouched
@@ -1426,32 +1470,7 @@ __global__ void __launch_bounds__(kBlock) k_round(DevPtrs d, Params P, int round
                         reserve(&d.owner[d.members[e]], key);
                 }
             } else {  // decide
-                uint32_t unused = 0, lost = 0;
-                for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
-                    const unsigned long long o = d.owner[d.members[e]];
-                    unused += o != 0ull ? 1u : 0u;
-                    lost |= (o != 0ull && o != key) ? 1u : 0u;
-                }
-                unused = group_sum8(unused);
-                lost = group_sum8(lost);
-                if (unused < cand_min(d, P, ci)) {
-                    if (sub == 0) d.status[ci] = kRejected;
-                } else if (lost == 0) {
-                    // every unused grain is this candidate's (owner == key)
-                    for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
-                        const uint32_t k = d.members[e];
-                        if (d.owner[k] != 0ull) {
-                            d.owner[k] = 0ull;
-                            d.taken[e] = 1;
-                        }
-                    }
-                    if (sub == 0) {
-                        d.mcount[ci] = unused;
-                        d.status[ci] = kAccepted;
-                    }
-                } else {
-                    still = sub == 0;
-                }
+                still = decide(d, P, ci, key, e0, e1, sub) && sub == 0;
             }
         }
         if (kPhase == 1) {
@@ -1521,7 +1540,8 @@ __global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, 
         // sums only read lanes that took the same branch)
         for (uint32_t i = group; i < n; i += kTailGroups) {
             const uint32_t ci = list[cur][i];
-            if (d.status[ci] != kUndecided) continue;
+            const uint8_t st = d.status[ci];
+            if (st != kUndecided && st != kCertain) continue;
             const uint32_t e0 = d.mem_off[ci], e1 = e0 + d.cand[ci].n;
             uint32_t unused = 0;
             for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
@@ -1532,14 +1552,14 @@ __global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, 
                 }
             }
             unused = group_sum8(unused);
-            if (unused < cand_min(d, P, ci) && sub == 0) d.status[ci] = kRejected;
+            if (unused < cand_min(d, P, ci) && st != kCertain && sub == 0) d.status[ci] = kRejected;
         }
         __threadfence_block();
         __syncthreads();
         // reserve
         for (uint32_t i = group; i < n; i += kTailGroups) {
             const uint32_t ci = list[cur][i];
-            if (d.status[ci] != kUndecided) continue;
+            if (d.status[ci] != kUndecided && d.status[ci] != kCertain) continue;
             const unsigned long long key = d.key[ci];
             const uint32_t e0 = d.mem_off[ci], e1 = e0 + d.cand[ci].n;
             for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup)
@@ -1550,32 +1570,10 @@ __global__ void __launch_bounds__(kTailBlock) k_merge_tail(DevPtrs d, Params P, 
         // decide
         for (uint32_t i = group; i < n; i += kTailGroups) {
             const uint32_t ci = list[cur][i];
-            if (d.status[ci] != kUndecided) continue;
+            if (d.status[ci] != kUndecided && d.status[ci] != kCertain) continue;
             const unsigned long long key = d.key[ci];
             const uint32_t e0 = d.mem_off[ci], e1 = e0 + d.cand[ci].n;
-            uint32_t unused = 0, lost = 0;
-            for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
-                const unsigned long long o = d.owner[d.members[e]];
-                unused += o != 0ull ? 1u : 0u;
-                lost |= (o != 0ull && o != key) ? 1u : 0u;
-            }
-            unused = group_sum8(unused);
-            lost = group_sum8(lost);
-            if (unused < cand_min(d, P, ci)) {
-                if (sub == 0) d.status[ci] = kRejected;
-            } else if (lost == 0) {
-                for (uint32_t e = e0 + sub; e < e1; e += kMergeGroup) {
-                    const uint32_t k = d.members[e];
-                    if (d.owner[k] != 0ull) {
-                        d.owner[k] = 0ull;
-                        d.taken[e] = 1;
-                    }
-                }
-                if (sub == 0) {
-                    d.mcount[ci] = unused;
-                    d.status[ci] = kAccepted;
-                }
-            } else if (sub == 0) {
+            if (decide(d, P, ci, key, e0, e1, sub) && sub == 0) {
                 const uint32_t slot = atomicAdd(&s_n[cur ^ 1], 1u);
                 list[cur ^ 1][slot] = ci;
             }
