@@ -1141,6 +1141,11 @@ k_count(DevPtrs d, Caps c, Params P) {
                 const int4 gi = d.sg[pq.x], gj = d.sg[pq.y];
                 const int dx = gj.x - gi.x, dy = gj.y - gi.y, dz = gj.z - gi.z;
                 const uint32_t th = seed_threshold(dx, dy, dz, P);
+                if constexpr (kEmit) {
+                    // the merge's priority key and threshold of the candidate
+                    d.key[idx] = cand_key(d.cand[idx].n, (uint32_t)gi.w, (uint32_t)gj.w);
+                    if (P.thr_num) d.cand_thr[idx] = th;
+                }
                 if (cur == lane) {
                     idx0 = idx;
                     th0 = th;
@@ -1245,7 +1250,8 @@ __device__ __forceinline__ uint32_t cand_before(const DevPtrs &d, uint32_t s) {
 // Candidates in seed order, one mask word per thread: positions from the
 // scan of the words' popcounts; their counts (for the member offsets); and
 // the seeds and candidates of each view (views are contiguous in anchor
-// order, so in seed and in candidate order too).
+// order, so in seed and in candidate order too). Keys and thresholds are
+// written by the member listing, which loads both seed grains anyway.
 __global__ void __launch_bounds__(kBlock) k_cand_scatter(DevPtrs d, Caps c, Params P) {
     const uint32_t ns = d.cnt->n_seeds_ok;
     for (uint32_t v = grid_tid(); v < d.desc->n_views; v += grid_threads()) {
@@ -1270,9 +1276,6 @@ __global__ void __launch_bounds__(kBlock) k_cand_scatter(DevPtrs d, Caps c, Para
             cd.v = d.view_of[pq.x];
             d.cand[pos] = cd;
             d.cand_n[pos] = n;
-            const int4 gi = d.sg[pq.x], gj = d.sg[pq.y];
-            if (P.thr_num) d.cand_thr[pos] = seed_threshold(gj.x - gi.x, gj.y - gi.y, gj.z - gi.z, P);
-            d.key[pos] = cand_key(n, (uint32_t)gi.w, (uint32_t)gj.w);
         }
     }
     add_spread(d.part64, 1, wave_sum(listed));
