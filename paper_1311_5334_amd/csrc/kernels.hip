@@ -1299,11 +1299,14 @@ __device__ __forceinline__ uint32_t cand_min(const DevPtrs &d, const Params &P, 
 //            each of its unused grains;
 //   decide   one holding every reservation of its unused grains has no
 //            undecided predecessor on them, so its unused set is final: it
-//            is accepted with that set if it still has n_min grains.
-// Accepted candidates of one round own disjoint grains, so their updates do
-// not interact, and a concurrent update can only hide grains taken by a
-// higher-priority accepted candidate. The grid-wide rounds fuse prune and
-// reserve into one pass; the tail kernel keeps the three phases.
+//            is accepted with that set if it still has n_min grains; one
+//            holding at least n_min of them but not all is sure to be
+//            accepted and takes the ones it holds at once (see decide).
+// Candidates taking grains in one round own disjoint grains, so their
+// updates do not interact, and a concurrent update can only hide grains
+// taken by a higher-priority candidate. The grid-wide rounds fuse prune and
+// reserve into one pass; the tail kernel keeps the three phases. A
+// candidate sure to be accepted is never pruned.
 
 constexpr int kMaxRounds = 256;
 constexpr int kWideRounds = 16;  // most grid-wide rounds (distinct key tags) before the tail
